@@ -1,0 +1,167 @@
+/*
+ * stagcg.h - C ABI of libstagcg.so, the MI355X (gfx950) staggered-fermion CG library.
+ *
+ * The library solves (4 m^2 - D_eo D_oe) x_e = b_e, where D is the staggered
+ * Dirac operator of Kim and Lee, "Multi GPU Performance of Conjugate Gradient
+ * Algorithm with Staggered Fermions" (Lattice 2010): Eq. (5) with the staggered
+ * phases folded into the links (Sec. 2), plus a three-hop (Naik) term with
+ * coefficient c_N, and Eq. (3) written on even sites.  The solver is the CG of
+ * Fig. 1, optionally with mixed-precision storage and reliable updates (the
+ * mixed precision that Sec. 5 announces), batching of many right-hand sides and
+ * lattices, and a learned preconditioner inside flexible CG.
+ *
+ * Conventions shared by every entry point
+ *  - dims = {Lx, Ly, Lz, Lt}; each even and >= 2.  Direction mu = 0..3 is x, y, z, t.
+ *  - Staggered phase eta_mu(n) = (-1)^(n_0 + ... + n_{mu-1}); time may be
+ *    antiperiodic, in which case a forward hop of length k from n picks up
+ *    (-1)^floor((n_t + k) / Lt).
+ *  - Link fields (inputs to stag_load_links): device complex128
+ *    [4][Lt][Lz][Ly][Lx][3][3] (real, imaginary interleaved); element [mu][n] is
+ *    U_mu(n), which multiplies the colour vector at n + mu (one-hop "fat" field)
+ *    or at n + 3 mu (three-hop "long" field).
+ *  - Colour-vector fields on one parity: device complex128 [nrhs][V/2][3],
+ *    site index cb = lex >> 1 with lex = x + Lx (y + Ly (z + Lz t)); parity of a
+ *    site is (x + y + z + t) mod 2.
+ *  - Streams: every call enqueues its device work on `stream` (a hipStream_t
+ *    passed as void*, NULL = the null stream).  stag_dslash and stag_apply_m are
+ *    asynchronous; the solvers synchronise before returning.
+ *  - Ownership: the caller owns every pointer it passes.  The library copies and
+ *    repacks links during stag_load_links; the inputs may be freed once the
+ *    stream has passed the call.  A lattice owns its packed links and all solver
+ *    workspace; stag_destroy_lattice frees them.
+ *  - Errors: every call returns a stag_status.  Arguments are validated before
+ *    any side effect (STAG_ERR_ARG).  HIP failures return STAG_ERR_HIP.  The
+ *    message of the last failure on the calling thread is stag_last_error().
+ *    No exception crosses the ABI.
+ *  - Thread safety: calls on different lattices may run concurrently; calls on
+ *    one lattice must be serialised by the caller.
+ */
+#ifndef STAGCG_H
+#define STAGCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stag_lattice_s* stag_lattice_t;
+typedef struct stag_net_s* stag_net_t;
+
+typedef enum {
+  STAG_OK = 0,
+  STAG_ERR_ARG = 1,            /* invalid argument (null pointer, bad size, odd extent, unpacked precision) */
+  STAG_ERR_HIP = 2,            /* a HIP runtime call failed */
+  STAG_ERR_NOMEM = 3,          /* device allocation failed */
+  STAG_ERR_STATE = 4,          /* call out of order (e.g. dslash before load_links) */
+  STAG_ERR_NOT_CONVERGED = 5,  /* max_iter or max_restarts reached; x holds the last iterate */
+  STAG_ERR_NAN = 6             /* a NaN/Inf or a non-positive d^dag A d appeared in a reduction */
+} stag_status;
+
+typedef enum { STAG_F64 = 0, STAG_F32 = 1, STAG_F16 = 2 } stag_prec;
+#define STAG_PREC_BIT(p) (1u << (p))
+
+typedef enum { STAG_PRECOND_NONE = 0, STAG_PRECOND_NET = 1 } stag_precond;
+
+/* Solver parameters.  Fill with stag_cg_params_default() and then override. */
+typedef struct {
+  double tol;                /* target true residual ||b - M x|| / ||b|| (default 1e-10) */
+  int32_t max_iter;          /* inner iterations per restart; <= 0: 3V/2 (the dimension N_dim of Fig. 1) */
+  int32_t prec;              /* stag_prec of the inner iteration; STAG_F64 = plain CG of Fig. 1 */
+  int32_t reliable_interval; /* mixed precision: iterations between FP64 residual recomputations (default 50) */
+  int32_t check_interval;    /* iterations between host convergence polls (default 16) */
+  int32_t max_restarts;      /* true-residual restarts after the iterated residual converged (default 5) */
+  int32_t precond;           /* stag_precond */
+  stag_net_t net;            /* network for STAG_PRECOND_NET */
+  int32_t stall_window;      /* FCG: fall back to plain CG if ||r_k|| > stall_ratio ||r_{k-w}|| (default 10) */
+  double stall_ratio;        /* default 0.9 */
+  int32_t profile;           /* 1: time every Dslash launch with HIP events (stag_cg_info.dslash_ms) */
+  int32_t history_len;       /* record the first history_len (alpha, beta) pairs per RHS into history */
+  double* history;           /* host [nrhs][history_len][2] or NULL */
+  int32_t reserved[8];
+} stag_cg_params;
+
+/* Per right-hand side result of a solve. */
+typedef struct {
+  int32_t iters;             /* inner iterations summed over restarts */
+  int32_t restarts;          /* true-residual restarts taken */
+  int32_t n_reliable;        /* mixed precision: FP64 residual recomputations */
+  int32_t fell_back;         /* FCG: 1 if the preconditioner stalled and plain CG finished the solve */
+  int32_t converged;         /* 1 if true_resid <= tol */
+  int32_t status;            /* stag_status of this right-hand side */
+  double true_resid;         /* ||b - M x|| / ||b|| of the returned x, computed in FP64 on the GPU */
+  double ms;                 /* wall time of the whole call (same for every RHS of a call) */
+  double dslash_ms;          /* profile=1: summed duration of the Dslash launches of the call */
+  int32_t dslash_calls;      /* profile=1: number of Dslash launches timed */
+  int32_t dslash_prec;       /* precision of the timed Dslash launches (inner iteration precision) */
+  double dslash_sites;       /* profile=1: output sites x RHS processed per timed launch, averaged */
+} stag_cg_info;
+
+/* One problem of a batched solve: a lattice with its own right-hand sides and masses. */
+typedef struct {
+  stag_lattice_t lat;
+  int32_t nrhs;
+  const double* mass;        /* host [nrhs] */
+  const void* b;             /* device complex128 [nrhs][V/2][3] */
+  void* x;                   /* device complex128 [nrhs][V/2][3]; in: initial guess, out: solution */
+} stag_problem;
+
+void stag_cg_params_default(stag_cg_params* prm);
+
+/* Lattice geometry (Sec. 2: the even-odd decomposition of the operator).
+ * dims: host int32[4] = {Lx, Ly, Lz, Lt}, each even and >= 2, product < 2^31.
+ * t_antiperiodic: 1 = antiperiodic time direction, 0 = periodic.
+ * Uses the current HIP device; the lattice stays bound to it. */
+stag_status stag_create_lattice(const int32_t dims[4], int32_t t_antiperiodic, stag_lattice_t* out);
+stag_status stag_destroy_lattice(stag_lattice_t lat);
+stag_status stag_lattice_info(stag_lattice_t lat, int32_t dims[4], int64_t* half_volume);
+
+/* Fold the phases, boundary signs and c_N into the links and repack them (Sec. 2,
+ * "the phase factor is multiplied to the gauge link"; Sec. 3.1 coalesced layout).
+ * fat, lng: device complex128 link fields (layout above); lng = NULL drops the
+ * three-hop term, leaving the paper's one-hop Eq. (5).  naik_coeff: c_N (-1/24
+ * for the improved action).  prec_mask: STAG_PREC_BIT of every storage precision
+ * to build (FP64 is always built: the true residual needs it).  Replaces any
+ * previously loaded links. */
+stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng, double naik_coeff,
+                            uint32_t prec_mask, void* stream);
+
+/* out = D_{p,1-p} in (Eq. (5) restricted to output parity p = out_parity).
+ * in: device complex128 [nrhs][V/2][3] on parity 1-p; out: same shape on parity p;
+ * in and out must not overlap.  prec selects the stored links and the
+ * arithmetic: STAG_F64 computes in FP64; STAG_F32 / STAG_F16 round `in` to that
+ * storage format, compute in FP32 and return the rounded result widened to
+ * complex128. */
+stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, void* out,
+                        int32_t nrhs, int32_t prec, void* stream);
+
+/* out = M in = 4 m^2 in - D_eo D_oe in on even sites (Eq. (3)), FP64.
+ * mass: host double[nrhs]; in, out: device complex128 [nrhs][V/2][3], not overlapping. */
+stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,
+                         int32_t nrhs, void* stream);
+
+/* Solve M x = b for each right-hand side by the CG of Fig. 1 (prm->prec = STAG_F64),
+ * by mixed-precision CG with reliable updates (STAG_F32 / STAG_F16), or by flexible
+ * CG with a network preconditioner (prm->precond).  Every solve ends with the
+ * FP64 true residual ||b - M x|| / ||b||, and restarts from x while it exceeds tol.
+ * mass: host double[nrhs]; b: device complex128 [nrhs][V/2][3]; x: same shape, the
+ * initial guess on entry (zero it for a cold start) and the solution on return.
+ * info: host [nrhs], filled on every return but STAG_ERR_ARG.  Returns STAG_OK if
+ * every RHS converged, otherwise the first failing RHS's status. */
+stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b, void* x, int32_t nrhs,
+                          const stag_cg_params* prm, stag_cg_info* info, void* stream);
+
+/* Solve several problems (lattices of different shapes, each with its own
+ * right-hand sides and masses) as one batch: every CG stage is one launch over
+ * all problems.  probs: host [nprob]; info: host [sum of nrhs], in problem order. */
+stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const stag_cg_params* prm,
+                                stag_cg_info* info, void* stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* stag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAGCG_H */

@@ -18,9 +18,10 @@ Staggered Fermions", Lattice 2010):
   * cg        - the conjugate-gradient loop of Fig. 1 with a true-residual check
   * fcg       - flexible CG with a preconditioner callback and stall fallback
   * quant     - FP32 / FP16-with-per-site-scale storage rules
+  * lowprec   - the operator applied in FP64 to inputs rounded as the storage formats round them
   * cost      - bytes and flops per site (Sec. 2 accounting)
   * net       - the gauge-covariant linear network used as a preconditioner
 
 Readings of the paper where it is silent are stated in each function.
 """
-from . import geometry, dslash, dense, free, cg, quant, cost  # noqa: F401
+from . import geometry, dslash, dense, free, cg, quant, cost, lowprec  # noqa: F401

@@ -1,0 +1,100 @@
+"""Reference for the low-precision Dslash: the operator evaluated exactly (FP64) on rounded inputs.
+
+The mixed-precision solver stores, for every output site n of parity p, the 16
+matrices that multiply its neighbours (the terms of Eq. (5) plus the three-hop
+terms, with eta, the boundary sign and c_N folded in), in the order
+    k = 4 mu + 0 : eta_mu(n) s(n,1) F_mu(n)                  neighbour n + mu
+    k = 4 mu + 1 : -eta_mu(n) s(n-mu,1) F_mu(n-mu)^dag       neighbour n - mu
+    k = 4 mu + 2 : c_N eta_mu(n) s(n,3) W_mu(n)              neighbour n + 3mu
+    k = 4 mu + 3 : -c_N eta_mu(n) s(n-3mu,3) W_mu(n-3mu)^dag neighbour n - 3mu
+and rounds them to binary32, or to binary16 with one binary32 scale per site for
+the eight one-hop matrices and one for the eight three-hop matrices.  Colour
+vectors are rounded per site (quant.py).  The functions here build those
+matrices from the definition, round them with the rules of quant.py, and apply
+them in FP64, so that the GPU's FP32 arithmetic can be bounded against them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import quant
+from .geometry import eta as eta_field, parity
+
+NAIK_COEFF = -1.0 / 24.0
+
+
+def site_matrices(fat, lng, dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF):
+    """Return (mats [V/2][16][3][3], nbr [V/2][16]) for the sites of parity out_parity."""
+    Lx, Ly, Lz, Lt = dims
+    L = np.array(dims)
+    par = parity(dims)
+    t, z, y, x = np.nonzero(par == out_parity)          # lexicographic order = cb order
+    n = np.stack([x, y, z, t], axis=1)
+    half = len(x)
+    mats = np.zeros((half, 16, 3, 3), dtype=np.complex128)
+    nbr = np.zeros((half, 16), dtype=np.int64)
+
+    def cb(m):
+        return (m[:, 0] + Lx * (m[:, 1] + Ly * (m[:, 2] + Lz * m[:, 3]))) // 2
+
+    def sign(mu, k, m):
+        if mu != 3 or not antiperiodic_t:
+            return np.ones(len(m))
+        return np.where(((m[:, 3] + k) // Lt) % 2 == 0, 1.0, -1.0)
+
+    for mu in range(4):
+        e = eta_field(mu, dims)[t, z, y, x]
+        for j, (k, U, c) in enumerate(((1, fat, 1.0), (3, lng, naik))):
+            fwd = n.copy()
+            fwd[:, mu] = (n[:, mu] + k) % L[mu]
+            bwd = n.copy()
+            bwd[:, mu] = (n[:, mu] - k) % L[mu]
+            nbr[:, 4 * mu + 2 * j] = cb(fwd)
+            nbr[:, 4 * mu + 2 * j + 1] = cb(bwd)
+            if U is None:
+                continue
+            Uf = U[mu, n[:, 3], n[:, 2], n[:, 1], n[:, 0]]
+            Ub = U[mu, bwd[:, 3], bwd[:, 2], bwd[:, 1], bwd[:, 0]]
+            mats[:, 4 * mu + 2 * j] = (c * e * sign(mu, k, n))[:, None, None] * Uf
+            mats[:, 4 * mu + 2 * j + 1] = (-c * e * sign(mu, k, bwd))[:, None, None] * np.conj(
+                np.swapaxes(Ub, -1, -2))
+    return mats, nbr
+
+
+def apply_site_matrices(mats, nbr, chi_half):
+    """out(n) = sum_k mats[n,k] chi(nbr[n,k]) in FP64."""
+    return np.einsum("nkab,nkb->na", mats, chi_half[nbr])
+
+
+def abs_bound_terms(mats, nbr, chi_half):
+    """sum_k |mats[n,k]| |chi(nbr[n,k])| per output component (for rounding-error bounds)."""
+    return np.einsum("nkab,nkb->na", np.abs(mats.real) + np.abs(mats.imag),
+                     np.abs(chi_half[nbr].real) + np.abs(chi_half[nbr].imag))
+
+
+def round_matrices(mats, prec: str):
+    """Round the 16 matrices of each site as the storage format does."""
+    if prec == "f64":
+        return mats
+    if prec == "f32":
+        return quant.to_f32(mats)
+    if prec == "f16":
+        out = np.empty_like(mats)
+        # groups: one-hop k in {4mu, 4mu+1}, three-hop k in {4mu+2, 4mu+3}, over all mu
+        k_fat = [4 * mu + d for mu in range(4) for d in (0, 1)]
+        k_long = [4 * mu + d for mu in range(4) for d in (2, 3)]
+        for ks in (k_fat, k_long):
+            codes, s = quant.quantize_link_group_f16(mats[:, ks])
+            out[:, ks] = quant.dequantize_link_group_f16(codes, s)
+        return out
+    raise ValueError(prec)
+
+
+def round_spinor(v, prec: str):
+    if prec == "f64":
+        return v
+    if prec == "f32":
+        return quant.to_f32(v)
+    if prec == "f16":
+        return quant.spinor_f16_roundtrip(v)
+    raise ValueError(prec)

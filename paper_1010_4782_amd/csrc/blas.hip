@@ -1,0 +1,320 @@
+// Fused CG vector stages and deterministic reductions (Fig. 1's vector algebra).
+//
+// Each stage is one launch over every right-hand side ("slot") of the batch.
+// Reductions are two-stage and deterministic: a wave64 shuffle tree plus an
+// LDS step per workgroup write one partial per (slot, tile); a finalize launch
+// with one workgroup per slot sums the partials in a fixed order and updates
+// the slot's FP64 scalars (alpha, beta, stopping state) on the device, so the
+// host never waits inside an iteration.
+#include "device.h"
+#include "launch.h"
+
+namespace stag {
+
+struct VecMap {
+  const ProbDev* pd;
+  int p, tile, r, slot, cb;
+  bool live;
+};
+
+__device__ __forceinline__ bool map_vec_block(const Batch& B, VecMap& m) {
+  const int bid = blockIdx.x;
+  m.p = find_problem(B, bid);
+  m.pd = B.probs + m.p;
+  const int local = bid - B.block_start[m.p];
+  const int groups = B.groups[m.p];
+  m.tile = local / groups;
+  m.r = local - m.tile * groups;
+  m.slot = m.pd->slot0 + m.r;
+  const int cb = m.tile * blockDim.x + threadIdx.x;
+  m.live = cb < m.pd->g.half;
+  m.cb = m.live ? cb : 0;
+  return true;
+}
+
+template <int P>
+__device__ __forceinline__ char* vec_ptr(const VecMap& m, int id) {
+  return reinterpret_cast<char*>(m.pd->vec[id]) + (long)m.r * m.pd->g.half * spinor_bytes(P);
+}
+
+__device__ __forceinline__ void write_partial(const Batch& B, const VecMap& m, int kind, double v) {
+  if (threadIdx.x == 0) B.partial[((long)m.slot * kPartialSlots + kind) * B.pstride + m.tile] = v;
+}
+
+// partial[kind] = |v|^2
+template <int P>
+__global__ __launch_bounds__(kMaxWG) void k_norm2(Batch B, int v_id, int kind, int gate) {
+  __shared__ double lds[4];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate)) return;
+  double s[1] = {0.0};
+  if (m.live) {
+    Cx<typename RealOf<P>::T> v[3];
+    load_spinor<P>(vec_ptr<P>(m, v_id), m.cb, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[0] += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+  }
+  block_sum<1>(s, lds);
+  write_partial(B, m, kind, s[0]);
+}
+
+// r -= alpha Ad ; partial[1] = |r|^2 (of the stored r)
+template <int P>
+__global__ __launch_bounds__(kMaxWG) void k_update_r(Batch B, int r_id, int ad_id) {
+  using T = typename RealOf<P>::T;
+  __shared__ double lds[4];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, 1)) return;
+  const T alpha = (T)B.scal[m.slot].alpha;
+  double s[1] = {0.0};
+  if (m.live) {
+    Cx<T> r[3], a[3];
+    char* rp = vec_ptr<P>(m, r_id);
+    load_spinor<P>(rp, m.cb, r);
+    load_spinor<P>(vec_ptr<P>(m, ad_id), m.cb, a);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c].re = fma(-alpha, a[c].re, r[c].re);
+      r[c].im = fma(-alpha, a[c].im, r[c].im);
+    }
+    store_spinor<P>(rp, m.cb, r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[0] += (double)r[c].re * r[c].re + (double)r[c].im * r[c].im;
+  }
+  block_sum<1>(s, lds);
+  write_partial(B, m, 1, s[0]);
+}
+
+// x += alpha d (x in precision PX) ; d = r + beta d
+template <int P, int PX>
+__global__ __launch_bounds__(kMaxWG) void k_update_xd(Batch B, int x_id, int r_id, int d_id) {
+  using T = typename RealOf<P>::T;
+  using TX = typename RealOf<PX>::T;
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, 2) || !m.live) return;
+  const Scal& sc = B.scal[m.slot];
+  const TX alpha = (TX)sc.alpha;
+  const T beta = (T)sc.beta;
+  Cx<T> d[3], r[3];
+  Cx<TX> x[3];
+  char* dp = vec_ptr<P>(m, d_id);
+  char* xp = vec_ptr<PX>(m, x_id);
+  load_spinor<P>(dp, m.cb, d);
+  load_spinor<P>(vec_ptr<P>(m, r_id), m.cb, r);
+  load_spinor<PX>(xp, m.cb, x);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    x[c].re = fma(alpha, (TX)d[c].re, x[c].re);
+    x[c].im = fma(alpha, (TX)d[c].im, x[c].im);
+    d[c].re = fma(beta, d[c].re, r[c].re);
+    d[c].im = fma(beta, d[c].im, r[c].im);
+  }
+  store_spinor<PX>(xp, m.cb, x);
+  store_spinor<P>(dp, m.cb, d);
+}
+
+template <int PS, int PD>
+__global__ __launch_bounds__(kMaxWG) void k_copy(Batch B, int src_id, int dst_id, int gate) {
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate) || !m.live) return;
+  Cx<typename RealOf<PS>::T> a[3];
+  load_spinor<PS>(vec_ptr<PS>(m, src_id), m.cb, a);
+  Cx<typename RealOf<PD>::T> b[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[c] = {(typename RealOf<PD>::T)a[c].re, (typename RealOf<PD>::T)a[c].im};
+  store_spinor<PD>(vec_ptr<PD>(m, dst_id), m.cb, b);
+}
+
+// x (f64) += x_lo (f32) ; x_lo = 0
+__global__ __launch_bounds__(kMaxWG) void k_add_lo_to_hi(Batch B, int gate) {
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate) || !m.live) return;
+  Cx<double> x[3];
+  Cx<float> xl[3];
+  char* xp = vec_ptr<P64>(m, V_X);
+  char* lp = vec_ptr<P32>(m, V_XL);
+  load_spinor<P64>(xp, m.cb, x);
+  load_spinor<P32>(lp, m.cb, xl);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    x[c].re += (double)xl[c].re;
+    x[c].im += (double)xl[c].im;
+    xl[c] = {0.f, 0.f};
+  }
+  store_spinor<P64>(xp, m.cb, x);
+  store_spinor<P32>(lp, m.cb, xl);
+}
+
+template <int P>
+__global__ __launch_bounds__(kMaxWG) void k_zero(Batch B, int v_id, int gate) {
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate) || !m.live) return;
+  Cx<typename RealOf<P>::T> z[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) z[c] = {0, 0};
+  store_spinor<P>(vec_ptr<P>(m, v_id), m.cb, z);
+}
+
+// One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.
+__global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
+                                                  double* hist, int hist_stride) {
+  __shared__ double lds[4];
+  const int slot = blockIdx.x;
+  int p = 0;
+  while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
+  if (!slot_on(B.scal, slot, gate)) return;
+  const int ntiles = ceil_div(B.probs[p].g.half, producer_wg);
+  const double* src = B.partial + ((long)slot * kPartialSlots + kind) * B.pstride;
+  double s[1] = {0.0};
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s[0] += src[i];
+  block_sum<1>(s, lds);
+  if (threadIdx.x != 0) return;
+  const double sum = s[0];
+  Scal& sc = B.scal[slot];
+  switch (what) {
+    case FIN_B2:
+      sc.b2 = sum;
+      sc.thr = sc.aux * sum;  // aux holds tol^2
+      break;
+    case FIN_START:
+      sc.delta = sum;
+      sc.iter = 0;
+      sc.flags &= ~kFlagMaxIter;
+      if (!isfinite(sum)) {
+        sc.flags |= kFlagNaN;
+        sc.state = 2;
+      } else {
+        sc.state = sum <= sc.thr ? 2 : 0;
+      }
+      break;
+    case FIN_ALPHA:
+      if (sc.state == 1) {
+        sc.state = 2;
+        break;
+      }
+      if (sc.state != 0) break;
+      sc.dAd = sum;
+      if (!(sum > 0.0) || !isfinite(sum)) {
+        sc.flags |= kFlagNaN;
+        sc.state = 2;
+        break;
+      }
+      sc.alpha = sc.delta / sum;
+      if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2] = sc.alpha;
+      break;
+    case FIN_BETA:
+      if (sc.state != 0) break;
+      if (!isfinite(sum)) {
+        sc.flags |= kFlagNaN;
+        sc.state = 2;
+        break;
+      }
+      sc.delta_old = sc.delta;
+      sc.delta = sum;
+      sc.beta = sum / sc.delta_old;
+      if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2 + 1] = sc.beta;
+      sc.iter += 1;
+      if (sum <= sc.thr) sc.state = 1;
+      if (sc.iter >= sc.max_iter) {
+        sc.state = 1;
+        sc.flags |= kFlagMaxIter;
+      }
+      break;
+    case FIN_TRUE:
+      sc.aux = sqrt(sum / sc.b2);
+      sc.delta = sum;
+      break;
+    case FIN_RELIABLE:
+      sc.delta = sum;
+      break;
+  }
+}
+
+// ---- launchers ------------------------------------------------------------------
+static inline int nblocks(const Batch& B) { return B.block_start[B.nprob]; }
+
+#define STAG_PREC_SWITCH(prec, KERNEL, ...)                     \
+  switch (prec) {                                               \
+    case P64: KERNEL<P64><<<nb, wg, 0, st>>>(__VA_ARGS__); break; \
+    case P32: KERNEL<P32><<<nb, wg, 0, st>>>(__VA_ARGS__); break; \
+    case P16: KERNEL<P16><<<nb, wg, 0, st>>>(__VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                       \
+  }
+
+hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  STAG_PREC_SWITCH(prec, k_norm2, B, v_id, kind, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_r(const BatchHost& bh, int prec, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  const int r_id = prec == P64 ? V_R : V_RL;
+  STAG_PREC_SWITCH(prec, k_update_r, B, r_id, V_AD);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_xd(const BatchHost& bh, int prec, int x_prec, int x_id, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  const int r_id = prec == P64 ? V_R : V_RL;
+  if (prec == P64 && x_prec == P64)
+    k_update_xd<P64, P64><<<nb, wg, 0, st>>>(B, x_id, r_id, V_D);
+  else if (prec == P32 && x_prec == P32)
+    k_update_xd<P32, P32><<<nb, wg, 0, st>>>(B, x_id, r_id, V_D);
+  else if (prec == P16 && x_prec == P32)
+    k_update_xd<P16, P32><<<nb, wg, 0, st>>>(B, x_id, r_id, V_D);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_vec(const BatchHost& bh, int src_prec, int src_id, int dst_prec, int dst_id, int gate, int wg,
+                           hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+#define STAG_COPY(A, C) \
+  if (src_prec == A && dst_prec == C) { k_copy<A, C><<<nb, wg, 0, st>>>(B, src_id, dst_id, gate); return hipGetLastError(); }
+  STAG_COPY(P64, P64) STAG_COPY(P64, P32) STAG_COPY(P64, P16) STAG_COPY(P32, P32) STAG_COPY(P16, P16)
+  STAG_COPY(P32, P64) STAG_COPY(P16, P64)
+#undef STAG_COPY
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_add_lo_to_hi(const BatchHost& bh, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  k_add_lo_to_hi<<<nb, wg, 0, st>>>(B, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_vec(const BatchHost& bh, int prec, int v_id, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  STAG_PREC_SWITCH(prec, k_zero, B, v_id, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, int producer_wg, double* hist,
+                           int hist_stride, hipStream_t st) {
+  if (bh.nslots == 0) return hipSuccess;
+  const Batch B = make_batch(bh, producer_wg, 1);
+  k_finalize<<<bh.nslots, 256, 0, st>>>(B, what, kind, gate, producer_wg, hist, hist_stride);
+  return hipGetLastError();
+}
+
+}  // namespace stag

@@ -1,0 +1,389 @@
+// extern "C" entry points of libstagcg.so (declared in include/stagcg.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "runtime.h"
+
+namespace stag {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+hipError_t DevBuf::ensure(size_t need) {
+  if (need <= bytes && ptr) return hipSuccess;
+  release();
+  if (need == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&ptr, need);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    bytes = 0;
+    return e;
+  }
+  bytes = need;
+  return hipSuccess;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+hipError_t HostBuf::ensure(size_t need) {
+  if (need <= bytes && ptr) return hipSuccess;
+  release();
+  if (need == 0) return hipSuccess;
+  hipError_t e = hipHostMalloc(&ptr, need, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    bytes = 0;
+    return e;
+  }
+  bytes = need;
+  return hipSuccess;
+}
+
+void HostBuf::release() {
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+void Ctl::release() {
+  for (int i = 0; i < kRing; ++i)
+    if (ring_ev[i]) {
+      (void)hipEventSynchronize(ring_ev[i]);
+      (void)hipEventDestroy(ring_ev[i]);
+      ring_ev[i] = nullptr;
+    }
+  probs.release();
+  scal.release();
+  partial.release();
+  hist.release();
+  h_scal.release();
+  h_probs.release();
+  ring_dev.release();
+  ring_host.release();
+}
+
+ProbDev prob_dev(const stag_lattice_s* lat, int nrhs, int slot0) {
+  ProbDev pd{};
+  pd.g = lat->g;
+  for (int p = 0; p < 3; ++p)
+    for (int par = 0; par < 2; ++par) pd.links[p][par] = lat->links[p][par].ptr;
+  for (int par = 0; par < 2; ++par) pd.lscale[par] = reinterpret_cast<const float*>(lat->lscale[par].ptr);
+  pd.nrhs = nrhs;
+  pd.slot0 = slot0;
+  return pd;
+}
+
+}  // namespace stag
+
+using namespace stag;
+
+stag_lattice_s::~stag_lattice_s() {
+  (void)hipDeviceSynchronize();
+  for (auto& a : links)
+    for (auto& b : a) b.release();
+  for (auto& b : lscale) b.release();
+  for (auto& b : vec) b.release();
+  for (auto& b : io_lo) b.release();
+  ctl.release();
+  for (auto ev : prof_events) (void)hipEventDestroy(ev);
+}
+
+#define STAG_GUARD_BEGIN try {
+#define STAG_GUARD_END                                   \
+  }                                                      \
+  catch (const std::bad_alloc&) {                        \
+    set_error("host allocation failed");                 \
+    return STAG_ERR_NOMEM;                               \
+  }                                                      \
+  catch (const std::exception& ex) {                     \
+    set_error(std::string("internal error: ") + ex.what()); \
+    return STAG_ERR_STATE;                               \
+  }
+
+namespace {
+
+stag_status arg_error(const char* m) {
+  set_error(m);
+  return STAG_ERR_ARG;
+}
+
+// A parameter block in device memory for an asynchronous call, staged through
+// pinned host memory.  Entries are reused round-robin once their event has passed.
+struct RingEntry {
+  char* host;
+  char* dev;
+  int idx;
+};
+
+stag_status ring_acquire(Ctl& c, size_t need, RingEntry& out) {
+  need = (need + 255) & ~size_t(255);
+  if (need > c.ring_entry) {
+    for (int i = 0; i < Ctl::kRing; ++i)
+      if (c.ring_used[i]) STAG_HIP_TRY(hipEventSynchronize(c.ring_ev[i]));
+    c.ring_dev.release();
+    c.ring_host.release();
+    c.ring_entry = std::max(need, size_t(8192));
+    STAG_HIP_TRY(c.ring_dev.ensure(c.ring_entry * Ctl::kRing));
+    STAG_HIP_TRY(c.ring_host.ensure(c.ring_entry * Ctl::kRing));
+    for (int i = 0; i < Ctl::kRing; ++i) c.ring_used[i] = false;
+  }
+  const int i = c.ring_next;
+  c.ring_next = (i + 1) % Ctl::kRing;
+  if (!c.ring_ev[i]) STAG_HIP_TRY(hipEventCreateWithFlags(&c.ring_ev[i], hipEventDisableTiming));
+  if (c.ring_used[i]) STAG_HIP_TRY(hipEventSynchronize(c.ring_ev[i]));
+  out.host = reinterpret_cast<char*>(c.ring_host.ptr) + i * c.ring_entry;
+  out.dev = reinterpret_cast<char*>(c.ring_dev.ptr) + i * c.ring_entry;
+  out.idx = i;
+  return STAG_OK;
+}
+
+stag_status ring_release(Ctl& c, const RingEntry& e, hipStream_t st) {
+  STAG_HIP_TRY(hipEventRecord(c.ring_ev[e.idx], st));
+  c.ring_used[e.idx] = true;
+  return STAG_OK;
+}
+
+// Set up a single-problem batch whose table, scalars and partials live in a ring entry.
+stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* const* vec_override, hipStream_t st,
+                         BatchHost& bh, RingEntry& e) {
+  const int pstride = ceil_div(L->g.half, kWave);
+  const size_t off_scal = (sizeof(ProbDev) + 255) & ~size_t(255);
+  const size_t off_part = off_scal + ((sizeof(Scal) * nrhs + 255) & ~size_t(255));
+  const size_t need = off_part + sizeof(double) * (size_t)nrhs * kPartialSlots * pstride;
+  stag_status s = ring_acquire(L->ctl, need, e);
+  if (s != STAG_OK) return s;
+  ProbDev pd = prob_dev(L, nrhs, 0);
+  for (int v = 0; v < kNumVec; ++v) pd.vec[v] = L->vec[v].ptr;
+  for (int v = 0; v < kNumVec; ++v)
+    if (vec_override[v]) pd.vec[v] = vec_override[v];
+  std::memcpy(e.host, &pd, sizeof(pd));
+  Scal* sc = reinterpret_cast<Scal*>(e.host + off_scal);
+  for (int r = 0; r < nrhs; ++r) {
+    Scal z{};
+    z.mass4 = mass ? 4.0 * mass[r] * mass[r] : 0.0;
+    sc[r] = z;
+  }
+  STAG_HIP_TRY(hipMemcpyAsync(e.dev, e.host, off_part, hipMemcpyHostToDevice, st));
+  bh.probs.assign(1, HostProb{L->g.half, nrhs, 0});
+  bh.d_probs = reinterpret_cast<const ProbDev*>(e.dev);
+  bh.d_scal = reinterpret_cast<Scal*>(e.dev + off_scal);
+  bh.d_partial = reinterpret_cast<double*>(e.dev + off_part);
+  bh.pstride = pstride;
+  bh.nslots = nrhs;
+  bh.max_half = L->g.half;
+  return STAG_OK;
+}
+
+stag_status check_lattice(stag_lattice_t lat) {
+  if (!lat) return arg_error("lattice is NULL");
+  if (!lat->loaded) {
+    set_error("load_links has not been called on this lattice");
+    return STAG_ERR_STATE;
+  }
+  int dev = -1;
+  STAG_HIP_TRY(hipGetDevice(&dev));
+  if (dev != lat->device) return arg_error("the current HIP device is not the lattice's device");
+  return STAG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void stag_cg_params_default(stag_cg_params* prm) {
+  if (!prm) return;
+  std::memset(prm, 0, sizeof(*prm));
+  prm->tol = 1e-10;
+  prm->max_iter = 0;
+  prm->prec = STAG_F64;
+  prm->reliable_interval = 50;
+  prm->check_interval = 16;
+  prm->max_restarts = 5;
+  prm->precond = STAG_PRECOND_NONE;
+  prm->net = nullptr;
+  prm->stall_window = 10;
+  prm->stall_ratio = 0.9;
+  prm->profile = 0;
+  prm->history_len = 0;
+  prm->history = nullptr;
+}
+
+const char* stag_last_error(void) { return g_last_error.c_str(); }
+
+stag_status stag_create_lattice(const int32_t dims[4], int32_t t_antiperiodic, stag_lattice_t* out) {
+  STAG_GUARD_BEGIN
+  if (!dims || !out) return arg_error("dims and out must not be NULL");
+  *out = nullptr;
+  long vol = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 2 || dims[i] % 2) return arg_error("every extent must be even and >= 2");
+    vol *= dims[i];
+    if (vol >= (1L << 31)) return arg_error("lattice volume must be below 2^31 sites");
+  }
+  if (t_antiperiodic != 0 && t_antiperiodic != 1) return arg_error("t_antiperiodic must be 0 or 1");
+  int dev = 0;
+  STAG_HIP_TRY(hipGetDevice(&dev));
+  auto* L = new stag_lattice_s();
+  for (int i = 0; i < 4; ++i) L->dims[i] = dims[i];
+  L->antiper = t_antiperiodic;
+  L->device = dev;
+  L->g = make_geo(L->dims);
+  *out = L;
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+stag_status stag_destroy_lattice(stag_lattice_t lat) {
+  STAG_GUARD_BEGIN
+  if (!lat) return arg_error("lattice is NULL");
+  delete lat;
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+stag_status stag_lattice_info(stag_lattice_t lat, int32_t dims[4], int64_t* half_volume) {
+  if (!lat) return arg_error("lattice is NULL");
+  if (dims)
+    for (int i = 0; i < 4; ++i) dims[i] = lat->dims[i];
+  if (half_volume) *half_volume = lat->g.half;
+  return STAG_OK;
+}
+
+stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng, double naik_coeff,
+                            uint32_t prec_mask, void* stream) {
+  STAG_GUARD_BEGIN
+  if (!lat) return arg_error("lattice is NULL");
+  if (!fat) return arg_error("fat links must not be NULL");
+  if (!std::isfinite(naik_coeff)) return arg_error("naik_coeff must be finite");
+  if (prec_mask & ~0x7u) return arg_error("prec_mask has unknown bits");
+  int dev = -1;
+  STAG_HIP_TRY(hipGetDevice(&dev));
+  if (dev != lat->device) return arg_error("the current HIP device is not the lattice's device");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prec_mask |= STAG_PREC_BIT(STAG_F64);
+  const size_t padded = (size_t)ceil_div(lat->g.half, kWave) * kWave;
+  lat->loaded = false;
+  for (int p = 0; p < 3; ++p) {
+    if (!(prec_mask & STAG_PREC_BIT(p))) {
+      for (auto& b : lat->links[p]) b.release();
+      continue;
+    }
+    for (int par = 0; par < 2; ++par) {
+      STAG_HIP_TRY(lat->links[p][par].ensure(padded * kLinks * link_bytes(p)));
+      float* ls = nullptr;
+      if (p == P16) {
+        STAG_HIP_TRY(lat->lscale[par].ensure(padded * 2 * sizeof(float)));
+        ls = reinterpret_cast<float*>(lat->lscale[par].ptr);
+      }
+      STAG_HIP_TRY(launch_pack_links(p, fat, lng, naik_coeff, lat->g, lat->antiper, par, lat->links[p][par].ptr, ls, st));
+    }
+  }
+  lat->built = prec_mask;
+  lat->has_long = lng != nullptr;
+  lat->naik = naik_coeff;
+  lat->loaded = true;
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, void* out, int32_t nrhs, int32_t prec,
+                        void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (out_parity != 0 && out_parity != 1) return arg_error("out_parity must be 0 or 1");
+  if (!in || !out) return arg_error("in and out must not be NULL");
+  if (in == out) return arg_error("in and out must not overlap");
+  if (nrhs < 1) return arg_error("nrhs must be >= 1");
+  if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
+  if (!(lat->built & STAG_PREC_BIT(prec))) return arg_error("the requested precision was not packed by load_links");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* ov[kNumVec] = {};
+  const long nsites = (long)lat->g.half * nrhs;
+  if (prec == STAG_F64) {
+    ov[V_D] = const_cast<void*>(in);
+    ov[V_T] = out;
+  } else {
+    STAG_HIP_TRY(lat->io_lo[0].ensure(spinor_field_bytes(lat, prec, nrhs)));
+    STAG_HIP_TRY(lat->io_lo[1].ensure(spinor_field_bytes(lat, prec, nrhs)));
+    STAG_HIP_TRY(launch_convert_from_f64(prec, in, lat->io_lo[0].ptr, nsites, st));
+    ov[V_D] = lat->io_lo[0].ptr;
+    ov[V_T] = lat->io_lo[1].ptr;
+  }
+  BatchHost bh;
+  RingEntry e;
+  s = single_batch(lat, nrhs, nullptr, ov, st, bh, e);
+  if (s != STAG_OK) return s;
+  const DslashShape sh = dslash_shape(lat, prec, nrhs, nrhs);
+  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
+  if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, nsites, st));
+  return ring_release(lat->ctl, e, st);
+  STAG_GUARD_END
+}
+
+stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out, int32_t nrhs,
+                         void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (!mass || !in || !out) return arg_error("mass, in and out must not be NULL");
+  if (in == out) return arg_error("in and out must not overlap");
+  if (nrhs < 1) return arg_error("nrhs must be >= 1");
+  for (int r = 0; r < nrhs; ++r)
+    if (!std::isfinite(mass[r])) return arg_error("mass must be finite");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  STAG_HIP_TRY(lat->vec[V_TMPO].ensure(spinor_field_bytes(lat, P64, nrhs)));
+  void* ov[kNumVec] = {};
+  ov[V_D] = const_cast<void*>(in);
+  ov[V_AD] = out;
+  BatchHost bh;
+  RingEntry e;
+  s = single_batch(lat, nrhs, mass, ov, st, bh, e);
+  if (s != STAG_OK) return s;
+  const DslashShape sh = dslash_shape(lat, P64, nrhs, nrhs);
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh.wg, sh.r, st));
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh.wg, sh.r, st));
+  return ring_release(lat->ctl, e, st);
+  STAG_GUARD_END
+}
+
+stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b, void* x, int32_t nrhs,
+                          const stag_cg_params* prm, stag_cg_info* info, void* stream) {
+  STAG_GUARD_BEGIN
+  if (!lat) return arg_error("lattice is NULL");
+  stag_problem p{lat, nrhs, mass, b, x};
+  return solve_batch(1, &p, prm, info, reinterpret_cast<hipStream_t>(stream));
+  STAG_GUARD_END
+}
+
+stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const stag_cg_params* prm,
+                                stag_cg_info* info, void* stream) {
+  STAG_GUARD_BEGIN
+  return solve_batch(nprob, probs, prm, info, reinterpret_cast<hipStream_t>(stream));
+  STAG_GUARD_END
+}
+
+}  // extern "C"
+
+namespace stag {
+
+DslashShape dslash_shape(const stag_lattice_s* lat, int prec, int nrhs, int total_rhs) {
+  (void)lat;
+  (void)prec;
+  (void)total_rhs;
+  DslashShape s;
+  s.wg = 256;
+  s.r = 1;
+  while (s.r < 8 && nrhs % (s.r * 2) == 0) s.r *= 2;
+  return s;
+}
+
+}  // namespace stag

@@ -1,0 +1,196 @@
+// Even-odd staggered Dslash for gfx950 (Eq. (5) with folded phases plus the
+// three-hop Naik term), one output site per lane and R right-hand sides per
+// lane so that every link load serves R colour vectors.
+//
+//   out_p(n) = sum_{k<16} L_k(n) in_{1-p}(n + delta_k),  delta_k in {+-mu, +-3mu}
+//
+// L_k are the packed, phase-, sign- and c_N-folded matrices (pack.hip).  The
+// link stream is the compulsory traffic (16 x 144 B per site in FP64) and is
+// read with non-temporal loads; neighbour colour vectors come through L1/L2,
+// which the XCD-aware block order keeps local.
+#include "device.h"
+#include "launch.h"
+
+namespace stag {
+
+template <int P, int R, int EPI>
+__global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
+                                                   int b_id, int gate) {
+  using T = typename RealOf<P>::T;
+  __shared__ double lds[R * 4];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = find_problem(B, bid);
+  const ProbDev* pd = B.probs + p;
+  const Geo g = pd->g;
+  const int local = bid - B.block_start[p];
+  const int groups = B.groups[p];
+  const int tile = local / groups;
+  const int r0 = (local - tile * groups) * R;
+  const int nrhs = pd->nrhs, slot0 = pd->slot0;
+
+  bool on[R];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    on[r] = (r0 + r < nrhs) && slot_on(B.scal, slot0 + r0 + r, gate);
+    any |= on[r];
+  }
+  if (!any) return;  // uniform over the workgroup
+
+  const int cb_raw = tile * blockDim.x + threadIdx.x;
+  const bool live = cb_raw < g.half;
+  const int cb = live ? cb_raw : g.half - 1;  // dead lanes read a valid site and store nothing
+  const Site s = site_of(cb, out_par, g);
+  const long blk = cb >> 6;
+  const int lane = cb & 63;
+
+  const long rstride = (long)g.half * spinor_bytes(P);
+  const char* in = reinterpret_cast<const char*>(pd->vec[in_id]) + (long)r0 * rstride;
+  const char* lbase = reinterpret_cast<const char*>(pd->links[P][out_par]);
+  float sc_fat = 1.f, sc_long = 1.f;
+  if (P == P16) {
+    const float* ls = pd->lscale[out_par] + blk * 2 * kWave + lane;
+    sc_fat = ls[0];
+    sc_long = ls[kWave];
+  }
+
+  Cx<T> acc[R][3];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = Cx<T>{T(0), T(0)};
+
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int hop = j < 2 ? g.h1[mu] : g.h3[mu];
+      const int nb = neighbour(s, g, mu, hop, (j & 1) == 0);
+      Cx<T> u[9];
+      load_link<P>(lbase, blk, 4 * mu + j, lane, j < 2 ? sc_fat : sc_long, u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!on[r]) continue;
+        Cx<T> v[3];
+        load_spinor<P>(in + r * rstride, nb, v);
+        matvec_acc(u, v, acc[r]);
+      }
+    }
+  }
+
+  char* out = reinterpret_cast<char*>(pd->vec[out_id]) + (long)r0 * rstride;
+  if (EPI == EPI_PLAIN) {
+    if (live)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (on[r]) store_spinor<P>(out + r * rstride, cb, acc[r]);
+    return;
+  }
+
+  const char* xb = reinterpret_cast<const char*>(pd->vec[x_id]) + (long)r0 * rstride;
+  double part[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    part[r] = 0.0;
+    if (!on[r]) continue;
+    const T a = (T)B.scal[slot0 + r0 + r].mass4;
+    Cx<T> xv[3], o[3];
+    load_spinor<P>(xb + r * rstride, cb, xv);
+    if (EPI == EPI_RESID) {
+      Cx<T> bv[3];
+      load_spinor<P>(reinterpret_cast<const char*>(pd->vec[b_id]) + (long)(r0 + r) * rstride, cb, bv);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        o[c] = Cx<T>{bv[c].re - a * xv[c].re + acc[r][c].re, bv[c].im - a * xv[c].im + acc[r][c].im};
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[c] = Cx<T>{a * xv[c].re - acc[r][c].re, a * xv[c].im - acc[r][c].im};
+    }
+    if (live) {
+      store_spinor<P>(out + r * rstride, cb, o);
+      if (EPI == EPI_XPAY_DOT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[r] += (double)xv[c].re * (double)o[c].re + (double)xv[c].im * (double)o[c].im;
+      } else if (EPI == EPI_RESID) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[r] += (double)o[c].re * (double)o[c].re + (double)o[c].im * (double)o[c].im;
+      }
+    }
+  }
+  if (EPI == EPI_XPAY) return;
+  block_sum<R>(part, lds);
+  if (threadIdx.x == 0) {
+    const int kind = EPI == EPI_XPAY_DOT ? 0 : 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) B.partial[((long)(slot0 + r0 + r) * kPartialSlots + kind) * B.pstride + tile] = part[r];
+  }
+}
+
+Batch make_batch(const BatchHost& bh, int wg, int r) {
+  Batch B{};
+  B.probs = bh.d_probs;
+  B.scal = bh.d_scal;
+  B.partial = bh.d_partial;
+  B.pstride = bh.pstride;
+  B.nprob = (int)bh.probs.size();
+  B.block_start[0] = 0;
+  for (int p = 0; p < B.nprob; ++p) {
+    B.tiles[p] = ceil_div(bh.probs[p].half, wg);
+    B.groups[p] = ceil_div(bh.probs[p].nrhs, r);
+    B.block_start[p + 1] = B.block_start[p] + B.tiles[p] * B.groups[p];
+  }
+  return B;
+}
+
+template <int P, int R>
+static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
+                           int gate, int wg, hipStream_t st) {
+  switch (epi) {
+    case EPI_PLAIN:
+      k_dslash<P, R, EPI_PLAIN><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      break;
+    case EPI_XPAY_DOT:
+      k_dslash<P, R, EPI_XPAY_DOT><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      break;
+    case EPI_RESID:
+      if (P != P64) return hipErrorInvalidValue;
+      k_dslash<P64, R, EPI_RESID><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      break;
+    case EPI_XPAY:
+      if (P != P64) return hipErrorInvalidValue;
+      k_dslash<P64, R, EPI_XPAY><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t dslash_p(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
+                           int gate, int wg, int r, hipStream_t st) {
+  switch (r) {
+    case 1: return dslash_r<P, 1>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 2: return dslash_r<P, 2>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 4: return dslash_r<P, 4>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 8: return dslash_r<P, 8>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
+                         int b_id, int gate, int wg, int r, hipStream_t st) {
+  if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
+  const Batch B = make_batch(bh, wg, r);
+  const int nblk = B.block_start[B.nprob];
+  if (nblk == 0) return hipSuccess;
+  switch (prec) {
+    case P64: return dslash_p<P64>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    case P32: return dslash_p<P32>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    case P16: return dslash_p<P16>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace stag

@@ -1,0 +1,69 @@
+// Host-side launchers of the HIP kernels (declared here, defined in the .hip files).
+#pragma once
+
+#include <vector>
+
+#include "stag_internal.h"
+
+namespace stag {
+
+enum Epi : int {
+  EPI_PLAIN = 0,     // out = D in
+  EPI_XPAY_DOT = 1,  // out = 4m^2 x - D in ; partial[kind 0] = Re <x, out>
+  EPI_RESID = 2,     // out = b - (4m^2 x - D in) ; partial[kind 1] = |out|^2   (FP64 only)
+  EPI_XPAY = 3       // out = 4m^2 x - D in                                      (FP64 only)
+};
+
+// Host mirror of a batch: sizes the launchers need to build the block map.
+struct HostProb {
+  int half;
+  int nrhs;
+  int slot0;
+};
+
+struct BatchHost {
+  std::vector<HostProb> probs;
+  const ProbDev* d_probs = nullptr;
+  Scal* d_scal = nullptr;
+  double* d_partial = nullptr;
+  int pstride = 0;
+  int nslots = 0;
+  int max_half = 0;
+};
+
+// Block map for a launch with `wg` sites per workgroup and `r` right-hand sides per lane.
+Batch make_batch(const BatchHost& bh, int wg, int r);
+
+hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
+                         int b_id, int gate, int wg, int r, hipStream_t st);
+
+// Vector stages of the solvers (every one is one launch over all slots of the batch).
+hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st);
+hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, int producer_wg, double* hist,
+                           int hist_stride, hipStream_t st);
+hipError_t launch_update_r(const BatchHost& bh, int prec, int wg, hipStream_t st);
+hipError_t launch_update_xd(const BatchHost& bh, int prec, int x_prec, int x_id, int wg, hipStream_t st);
+hipError_t launch_copy_vec(const BatchHost& bh, int src_prec, int src_id, int dst_prec, int dst_id, int gate,
+                           int wg, hipStream_t st);
+hipError_t launch_add_lo_to_hi(const BatchHost& bh, int gate, int wg, hipStream_t st);  // x += x_lo ; x_lo = 0
+hipError_t launch_zero_vec(const BatchHost& bh, int prec, int v_id, int gate, int wg, hipStream_t st);
+
+// Finalize modes (one workgroup per slot, deterministic order).
+enum Fin : int {
+  FIN_B2 = 0,        // b2 = sum ; thr = tol^2 * b2 (tol from aux)
+  FIN_START = 1,     // delta = sum ; state = (delta <= thr) ? 1 : 0 ; iter = 0
+  FIN_ALPHA = 2,     // state 1 -> 2 ; else alpha = delta / dAd (breakdown -> NaN flag, state 2)
+  FIN_BETA = 3,      // delta_old = delta ; delta = sum ; beta ; iter++ ; stop test
+  FIN_TRUE = 4,      // aux = sqrt(sum / b2) (true residual)
+  FIN_RELIABLE = 5   // delta = sum (after the FP64 residual recomputation)
+};
+
+// Packing and conversions.
+hipError_t launch_pack_links(int prec, const void* fat, const void* lng, double naik, const Geo& g, int antiper,
+                             int par, void* out, float* lscale, hipStream_t st);
+hipError_t launch_convert_from_f64(int prec, const void* in, void* out, long nsites, hipStream_t st);
+hipError_t launch_convert_to_f64(int prec, const void* in, void* out, long nsites, hipStream_t st);
+
+Geo make_geo(const int dims[4]);
+
+}  // namespace stag

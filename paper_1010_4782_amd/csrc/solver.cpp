@@ -1,0 +1,368 @@
+// CG drivers: plain FP64 CG (Fig. 1) and mixed-precision CG with reliable
+// updates, over a batch of problems (one or more lattices, each with its own
+// right-hand sides and masses).  Every stage is one launch over the whole
+// batch; alpha, beta and the stopping state live on the device, and the host
+// only polls the per-slot state every `check_interval` iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <set>
+
+#include "runtime.h"
+
+namespace stag {
+
+namespace {
+
+constexpr int kVecWG = 256;
+
+struct Run {
+  std::vector<stag_lattice_s*> lats;
+  BatchHost bh;
+  Ctl* ctl = nullptr;
+  hipStream_t st = nullptr;
+  int prec = P64;
+  DslashShape shape;
+  int hist_len = 0;
+  bool profile = false;
+  std::vector<hipEvent_t>* events = nullptr;
+  size_t ev_used = 0;
+  Scal* h_scal = nullptr;
+};
+
+stag_status fail_arg(const std::string& m) {
+  set_error(m);
+  return STAG_ERR_ARG;
+}
+
+// STAG_DEBUG=1 in the environment prints the per-slot scalars at every host poll.
+bool debug_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("STAG_DEBUG");
+    return v && v[0] == '1';
+  }();
+  return on;
+}
+
+hipError_t pull_scal(Run& R, const char* where = "") {
+  hipError_t e = hipMemcpyAsync(R.h_scal, R.bh.d_scal, sizeof(Scal) * R.bh.nslots, hipMemcpyDeviceToHost, R.st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(R.st);
+  if (e == hipSuccess && debug_enabled())
+    for (int s = 0; s < R.bh.nslots; ++s) {
+      const Scal& c = R.h_scal[s];
+      std::fprintf(stderr, "[stag] %-10s slot %d state %d iter %d flags %d delta %.6e dAd %.6e alpha %.6e beta %.6e aux %.6e\n",
+                   where, s, c.state, c.iter, c.flags, c.delta, c.dAd, c.alpha, c.beta, c.aux);
+    }
+  return e;
+}
+
+hipError_t push_scal(Run& R) {
+  hipError_t e = hipMemcpyAsync(R.bh.d_scal, R.h_scal, sizeof(Scal) * R.bh.nslots, hipMemcpyHostToDevice, R.st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(R.st);
+}
+
+hipError_t record(Run& R) {
+  if (!R.profile) return hipSuccess;
+  if (R.ev_used == R.events->size()) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    R.events->push_back(ev);
+  }
+  return hipEventRecord((*R.events)[R.ev_used++], R.st);
+}
+
+// V_R = b - M x (FP64), aux = ||V_R|| / ||b||, delta = |V_R|^2, for slots passing `gate`.
+hipError_t true_residual(Run& R, int gate) {
+  const DslashShape s64 = R.shape;
+  hipError_t e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_X, V_TMPO, 0, 0, gate, s64.wg, s64.r, R.st);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_RESID, 0, V_TMPO, V_R, V_X, V_B, gate, s64.wg, s64.r, R.st);
+  if (e == hipSuccess) e = launch_finalize(R.bh, FIN_TRUE, 1, gate, s64.wg, nullptr, 0, R.st);
+  return e;
+}
+
+// One CG iteration in precision P (x accumulated in precision PX at x_id).
+hipError_t iteration(Run& R, int x_prec, int x_id, double* d_hist) {
+  const int P = R.prec;
+  hipError_t e = record(R);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape.wg, R.shape.r, R.st);
+  if (e == hipSuccess) e = record(R);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape.wg, R.shape.r, R.st);
+  if (e == hipSuccess) e = record(R);
+  if (e == hipSuccess) e = launch_finalize(R.bh, FIN_ALPHA, 0, 2, R.shape.wg, d_hist, R.hist_len, R.st);
+  if (e == hipSuccess) e = launch_update_r(R.bh, P, kVecWG, R.st);
+  if (e == hipSuccess) e = launch_finalize(R.bh, FIN_BETA, 1, 1, kVecWG, d_hist, R.hist_len, R.st);
+  if (e == hipSuccess) e = launch_update_xd(R.bh, P, x_prec, x_id, kVecWG, R.st);
+  return e;
+}
+
+}  // namespace
+
+stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_params* prm_in, stag_cg_info* info,
+                        hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  stag_cg_params prm;
+  if (prm_in) prm = *prm_in; else stag_cg_params_default(&prm);
+  if (nprob < 1 || nprob > kMaxProb) return fail_arg("nprob must be in [1, 16]");
+  if (!probs || !info) return fail_arg("probs and info must not be NULL");
+  if (!(prm.tol > 0.0) || !std::isfinite(prm.tol)) return fail_arg("tol must be a positive finite number");
+  if (prm.prec < STAG_F64 || prm.prec > STAG_F16) return fail_arg("prec must be STAG_F64, STAG_F32 or STAG_F16");
+  if (prm.precond != STAG_PRECOND_NONE) return fail_arg("this entry point solves without a preconditioner; use the FCG driver");
+  if (prm.check_interval <= 0) prm.check_interval = 16;
+  if (prm.reliable_interval <= 0) prm.reliable_interval = 50;
+  if (prm.max_restarts < 0) prm.max_restarts = 0;
+  if (prm.history_len < 0 || (prm.history_len > 0 && !prm.history)) return fail_arg("history_len > 0 needs a history buffer");
+
+  Run R;
+  R.st = st;
+  R.prec = prm.prec;
+  R.hist_len = prm.history_len;
+  R.profile = prm.profile != 0;
+  std::set<stag_lattice_s*> seen;
+  int nslots = 0, dev = -1;
+  hipGetDevice(&dev);
+  for (int p = 0; p < nprob; ++p) {
+    const stag_problem& q = probs[p];
+    if (!q.lat) return fail_arg("problem lattice is NULL");
+    if (!q.lat->loaded) { set_error("load_links has not been called on a lattice of the batch"); return STAG_ERR_STATE; }
+    if (q.nrhs < 1) return fail_arg("nrhs must be >= 1");
+    if (!q.mass || !q.b || !q.x) return fail_arg("mass, b and x must not be NULL");
+    if (!(q.lat->built & STAG_PREC_BIT(prm.prec))) return fail_arg("the requested precision was not packed by load_links");
+    if (q.lat->device != dev) return fail_arg("lattice belongs to another device than the current one");
+    if (!seen.insert(q.lat).second) return fail_arg("a lattice may appear only once per batch (merge its right-hand sides)");
+    for (int r = 0; r < q.nrhs; ++r)
+      if (!std::isfinite(q.mass[r])) return fail_arg("mass must be finite");
+    nslots += q.nrhs;
+  }
+  const bool mixed = prm.prec != STAG_F64;
+
+  // ---- workspace and tables ----
+  Ctl& ctl = probs[0].lat->ctl;
+  R.ctl = &ctl;
+  int max_half = 0;
+  R.bh.probs.clear();
+  std::vector<ProbDev> table(nprob);
+  int slot = 0;
+  int rdiv = 8;
+  for (int p = 0; p < nprob; ++p) {
+    stag_lattice_s* L = probs[p].lat;
+    const int n = probs[p].nrhs;
+    R.lats.push_back(L);
+    const int P = prm.prec;
+    STAG_HIP_TRY(L->vec[V_R].ensure(spinor_field_bytes(L, P64, n)));
+    STAG_HIP_TRY(L->vec[V_TMPO].ensure(spinor_field_bytes(L, P64, n)));
+    STAG_HIP_TRY(L->vec[V_D].ensure(spinor_field_bytes(L, P, n)));
+    STAG_HIP_TRY(L->vec[V_AD].ensure(spinor_field_bytes(L, P, n)));
+    STAG_HIP_TRY(L->vec[V_T].ensure(spinor_field_bytes(L, P, n)));
+    if (mixed) {
+      STAG_HIP_TRY(L->vec[V_RL].ensure(spinor_field_bytes(L, P, n)));
+      STAG_HIP_TRY(L->vec[V_XL].ensure(spinor_field_bytes(L, P32, n)));
+    }
+    ProbDev pd = prob_dev(L, n, slot);
+    for (int v = 0; v < kNumVec; ++v) pd.vec[v] = L->vec[v].ptr;
+    pd.vec[V_B] = const_cast<void*>(probs[p].b);
+    pd.vec[V_X] = probs[p].x;
+    table[p] = pd;
+    R.bh.probs.push_back(HostProb{L->g.half, n, slot});
+    max_half = std::max(max_half, L->g.half);
+    slot += n;
+    while (rdiv > 1 && n % rdiv) rdiv >>= 1;
+  }
+  R.bh.nslots = nslots;
+  R.bh.max_half = max_half;
+  R.bh.pstride = ceil_div(max_half, kWave);
+  STAG_HIP_TRY(ctl.probs.ensure(sizeof(ProbDev) * kMaxProb));
+  STAG_HIP_TRY(ctl.scal.ensure(sizeof(Scal) * nslots));
+  STAG_HIP_TRY(ctl.partial.ensure(sizeof(double) * (size_t)nslots * kPartialSlots * R.bh.pstride));
+  STAG_HIP_TRY(ctl.h_scal.ensure(sizeof(Scal) * nslots));
+  STAG_HIP_TRY(ctl.h_probs.ensure(sizeof(ProbDev) * kMaxProb));
+  double* d_hist = nullptr;
+  if (R.hist_len > 0) {
+    STAG_HIP_TRY(ctl.hist.ensure(sizeof(double) * 2 * (size_t)nslots * R.hist_len));
+    d_hist = reinterpret_cast<double*>(ctl.hist.ptr);
+    STAG_HIP_TRY(hipMemsetAsync(d_hist, 0, sizeof(double) * 2 * (size_t)nslots * R.hist_len, st));
+  }
+  R.bh.d_probs = reinterpret_cast<const ProbDev*>(ctl.probs.ptr);
+  R.bh.d_scal = reinterpret_cast<Scal*>(ctl.scal.ptr);
+  R.bh.d_partial = reinterpret_cast<double*>(ctl.partial.ptr);
+  R.h_scal = reinterpret_cast<Scal*>(ctl.h_scal.ptr);
+  R.events = &probs[0].lat->prof_events;
+  {
+    int total = 0;
+    for (int p = 0; p < nprob; ++p) total += probs[p].nrhs;
+    R.shape = dslash_shape(probs[0].lat, prm.prec, rdiv, total);
+    R.shape.r = std::min(R.shape.r, rdiv);
+  }
+  std::memcpy(ctl.h_probs.ptr, table.data(), sizeof(ProbDev) * nprob);
+  STAG_HIP_TRY(hipMemcpyAsync(ctl.probs.ptr, ctl.h_probs.ptr, sizeof(ProbDev) * nprob, hipMemcpyHostToDevice, st));
+
+  // ---- scalars ----
+  std::vector<int> passes(nslots, 0), iters(nslots, 0), n_rel(nslots, 0);
+  slot = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const int half = probs[p].lat->g.half;
+    for (int r = 0; r < probs[p].nrhs; ++r, ++slot) {
+      Scal s{};
+      s.mass4 = 4.0 * probs[p].mass[r] * probs[p].mass[r];
+      s.aux = prm.tol * prm.tol;
+      s.max_iter = prm.max_iter > 0 ? prm.max_iter : 3 * half;
+      s.hist_len = R.hist_len;
+      s.state = 0;
+      R.h_scal[slot] = s;
+    }
+  }
+  STAG_HIP_TRY(push_scal(R));
+  STAG_HIP_TRY(launch_norm2(R.bh, P64, V_B, 1, 3, kVecWG, st));
+  STAG_HIP_TRY(launch_finalize(R.bh, FIN_B2, 1, 3, kVecWG, nullptr, 0, st));
+  STAG_HIP_TRY(pull_scal(R));
+  std::vector<char> zero_src(nslots, 0);
+  bool any_zero = false;
+  for (int s = 0; s < nslots; ++s) any_zero |= (zero_src[s] = R.h_scal[s].b2 == 0.0) != 0;
+  if (any_zero) {
+    // b = 0 has the solution x = 0: zero those x and leave the slots finished.
+    for (int s = 0; s < nslots; ++s) R.h_scal[s].state = zero_src[s] ? 0 : 3;
+    STAG_HIP_TRY(push_scal(R));
+    STAG_HIP_TRY(launch_zero_vec(R.bh, P64, V_X, 1, kVecWG, st));
+    for (int s = 0; s < nslots; ++s) {
+      R.h_scal[s].state = zero_src[s] ? 3 : 0;
+      if (zero_src[s]) R.h_scal[s].aux = 0.0;
+    }
+    STAG_HIP_TRY(push_scal(R));
+  }
+
+  // ---- restart loop: r = b - M x (FP64), decide, iterate ----
+  STAG_HIP_TRY(true_residual(R, 0));
+  const int x_prec = mixed ? P32 : P64;
+  const int x_id = mixed ? V_XL : V_X;
+  std::vector<int> done_status(nslots, STAG_OK);
+  for (;;) {
+    STAG_HIP_TRY(pull_scal(R, "classify"));
+    bool any_run = false;
+    for (int s = 0; s < nslots; ++s) {
+      Scal& sc = R.h_scal[s];
+      if (sc.state == 3) continue;
+      iters[s] += sc.iter;
+      if (sc.aux <= prm.tol) {
+        sc.state = 3;
+        done_status[s] = STAG_OK;
+      } else if ((sc.flags & kFlagNaN) || !std::isfinite(sc.aux)) {
+        sc.state = 3;
+        done_status[s] = STAG_ERR_NAN;
+      } else if (passes[s] > prm.max_restarts) {
+        sc.state = 3;
+        done_status[s] = STAG_ERR_NOT_CONVERGED;
+      } else {
+        sc.state = 0;
+        sc.iter = 0;
+        sc.flags = 0;
+        passes[s] += 1;
+        any_run = true;
+      }
+    }
+    STAG_HIP_TRY(push_scal(R));
+    if (!any_run) break;
+    if (!mixed) {
+      STAG_HIP_TRY(launch_copy_vec(R.bh, P64, V_R, P64, V_D, 1, kVecWG, st));
+      for (;;) {
+        for (int i = 0; i < prm.check_interval; ++i) STAG_HIP_TRY(iteration(R, x_prec, x_id, d_hist));
+        STAG_HIP_TRY(pull_scal(R));
+        bool running = false;
+        for (int s = 0; s < nslots; ++s) running |= R.h_scal[s].state == 0;
+        if (!running) break;
+      }
+    } else {
+      const int P = prm.prec;
+      STAG_HIP_TRY(launch_copy_vec(R.bh, P64, V_R, P, V_RL, 1, kVecWG, st));
+      STAG_HIP_TRY(launch_copy_vec(R.bh, P, V_RL, P, V_D, 1, kVecWG, st));
+      STAG_HIP_TRY(launch_zero_vec(R.bh, P32, V_XL, 1, kVecWG, st));
+      int since = 0;
+      for (;;) {
+        for (int i = 0; i < prm.check_interval; ++i) STAG_HIP_TRY(iteration(R, x_prec, x_id, d_hist));
+        since += prm.check_interval;
+        STAG_HIP_TRY(pull_scal(R, "poll-mp"));
+        bool running = false;
+        for (int s = 0; s < nslots; ++s) running |= R.h_scal[s].state == 0;
+        if (running && since < prm.reliable_interval) continue;
+        // reliable update for running or just-stopped slots: x += x_lo, r = b - M x in FP64, r_lo = r.
+        // A slot that stopped early in the last batch of iterations has moved on to state 2; bring it
+        // back to 1 (unless it broke down) so that the update covers it.
+        since = 0;
+        for (int s = 0; s < nslots; ++s) {
+          Scal& sc = R.h_scal[s];
+          if (sc.state == 2 && !(sc.flags & kFlagNaN)) sc.state = 1;
+        }
+        STAG_HIP_TRY(push_scal(R));
+        STAG_HIP_TRY(launch_add_lo_to_hi(R.bh, 2, kVecWG, st));
+        STAG_HIP_TRY(true_residual(R, 2));
+        STAG_HIP_TRY(launch_copy_vec(R.bh, P64, V_R, P, V_RL, 2, kVecWG, st));
+        STAG_HIP_TRY(pull_scal(R, "reliable"));
+        bool cont = false;
+        for (int s = 0; s < nslots; ++s) {
+          Scal& sc = R.h_scal[s];
+          if (sc.state > 1) continue;
+          n_rel[s] += 1;
+          if (sc.aux <= prm.tol || (sc.flags & kFlagMaxIter)) {
+            sc.state = 2;  // the outer loop classifies it
+          } else {
+            sc.state = 0;
+            cont = true;
+          }
+        }
+        STAG_HIP_TRY(push_scal(R));
+        if (!cont) break;
+      }
+    }
+    STAG_HIP_TRY(true_residual(R, 0));
+  }
+
+  // ---- results ----
+  std::vector<double> hist;
+  if (R.hist_len > 0) {
+    hist.resize(2 * (size_t)nslots * R.hist_len);
+    STAG_HIP_TRY(hipMemcpyAsync(hist.data(), d_hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  STAG_HIP_TRY(hipStreamSynchronize(st));
+  if (R.hist_len > 0) std::memcpy(prm.history, hist.data(), hist.size() * sizeof(double));
+  double dms = 0.0;
+  int dcalls = 0;
+  if (R.profile) {
+    for (size_t i = 0; i + 2 < R.ev_used; i += 3) {
+      float a = 0.f, b = 0.f;
+      STAG_HIP_TRY(hipEventElapsedTime(&a, (*R.events)[i], (*R.events)[i + 1]));
+      STAG_HIP_TRY(hipEventElapsedTime(&b, (*R.events)[i + 1], (*R.events)[i + 2]));
+      dms += a + b;
+      dcalls += 2;
+    }
+  }
+  double sites = 0.0;
+  for (int p = 0; p < nprob; ++p) sites += (double)probs[p].lat->g.half * probs[p].nrhs;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  stag_status first_bad = STAG_OK;
+  for (int s = 0; s < nslots; ++s) {
+    stag_cg_info& o = info[s];
+    std::memset(&o, 0, sizeof(o));
+    o.iters = iters[s];
+    o.restarts = std::max(0, passes[s] - 1);
+    o.n_reliable = n_rel[s];
+    o.true_resid = R.h_scal[s].aux;
+    o.converged = done_status[s] == STAG_OK;
+    o.status = done_status[s];
+    o.ms = ms;
+    o.dslash_ms = dms;
+    o.dslash_calls = dcalls;
+    o.dslash_prec = prm.prec;
+    o.dslash_sites = sites;
+    if (first_bad == STAG_OK && done_status[s] != STAG_OK) first_bad = (stag_status)done_status[s];
+  }
+  if (first_bad != STAG_OK)
+    set_error(first_bad == STAG_ERR_NAN ? "a reduction produced NaN/Inf or a non-positive d^dag A d"
+                                        : "the solve did not reach the requested true residual");
+  return first_bad;
+}
+
+}  // namespace stag

@@ -1,0 +1,102 @@
+// Internal types shared by the host runtime and the HIP kernels of libstagcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stag {
+
+constexpr int kWave = 64;        // gfx950 wavefront
+constexpr int kMaxWG = 256;      // largest workgroup any kernel is launched with
+constexpr int kLinks = 16;       // packed matrices per output site: 4 directions x {fat fwd, fat bwd, long fwd, long bwd}
+constexpr int kMaxProb = 16;     // problems per batched launch
+constexpr int kPartialSlots = 2; // reduction partials per slot kept apart (dot and norm)
+
+enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
+
+// Storage of one packed link per lane: 9 complex numbers.
+__host__ __device__ constexpr int link_bytes(int p) { return p == P64 ? 144 : (p == P32 ? 72 : 36); }
+// Storage of one colour vector (3 complex) per site.  f16: six binary16 codes + one binary32 scale.
+__host__ __device__ constexpr int spinor_bytes(int p) { return p == P64 ? 48 : (p == P32 ? 24 : 16); }
+
+// Lattice geometry in the even-odd index cb = lex >> 1.
+struct Geo {
+  int L[4];        // Lx, Ly, Lz, Lt
+  int Xh;          // Lx / 2
+  int half;        // V / 2
+  int stride[4];   // cb distance of one step in y, z, t (stride[0] unused: x is handled by parity)
+  int h1[4];       // 1 mod L_mu
+  int h3[4];       // 3 mod L_mu
+};
+
+// Per right-hand-side solver state ("slot"), resident on the device.
+// state: 0 running, 1 stopped in this iteration (x update still pending), 2 stopped,
+//        3 finished (excluded from every stage until the host restarts it).
+struct Scal {
+  double b2;         // ||b||^2
+  double thr;        // stopping threshold on r^dag r
+  double delta;      // r^dag r (current)
+  double delta_old;
+  double dAd;        // Re d^dag A d
+  double alpha;
+  double beta;
+  double mass4;      // 4 m^2
+  double rz;         // FCG: <z, r>
+  double rz_new;     // FCG
+  double aux;        // scratch scalar (true residual, stall monitor)
+  int state;
+  int iter;          // iterations since the last (re)start
+  int max_iter;
+  int flags;         // bit 0: NaN / breakdown, bit 1: hit max_iter
+  int hist_len;      // number of (alpha, beta) pairs to record
+  int pad[3];
+};
+static_assert(sizeof(Scal) % 8 == 0, "Scal alignment");
+
+enum ScalFlags : int { kFlagNaN = 1, kFlagMaxIter = 2 };
+
+// Vector roles in a solver workspace (one [nrhs][V/2][3] array per role and problem).
+enum VecId : int {
+  V_B = 0,     // f64 source (caller's)
+  V_X,         // f64 solution (caller's)
+  V_R,         // f64 residual
+  V_D,         // search direction (inner precision)
+  V_AD,        // A d (inner precision)
+  V_T,         // odd-parity temporary (inner precision)
+  V_RL,        // low-precision residual (mixed precision)
+  V_XL,        // f32 low-precision solution accumulator (mixed precision)
+  V_TMP,       // f64 even temporary
+  V_TMPO,      // f64 odd temporary
+  V_Z,         // FCG: preconditioned residual
+  V_RPREV,     // FCG: previous residual
+  V_NETA,      // network activations
+  V_NETB,
+  kNumVec
+};
+
+// One problem as the kernels see it.
+struct ProbDev {
+  Geo g;
+  const void* links[3][2];  // packed links per storage precision and output parity (null if not built)
+  const float* lscale[2];   // f16 link-group scales per output parity (null if not built)
+  void* vec[kNumVec];
+  int nrhs;
+  int slot0;                // first scalar slot of this problem
+  int pad[2];
+};
+
+// Arguments of a batched launch: problems and where each starts in the block space.
+struct Batch {
+  const ProbDev* probs;     // device table
+  Scal* scal;               // device [nslots]
+  double* partial;          // device [nslots][kPartialSlots][pstride]
+  int pstride;              // partial entries per slot and kind
+  int nprob;
+  int block_start[kMaxProb + 1];
+  int tiles[kMaxProb];      // site tiles per RHS group
+  int groups[kMaxProb];     // RHS groups per problem
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace stag

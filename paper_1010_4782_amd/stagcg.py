@@ -1,0 +1,165 @@
+"""Python binding of libstagcg.so: the same entry points as include/stagcg.h, taking torch tensors.
+
+torch supplies device memory and the HIP stream; every step of the operator and
+the solvers runs in the library's kernels.  Tensors are complex128 on the GPU:
+links [4][Lt][Lz][Ly][Lx][3][3], even-odd vectors [nrhs][V/2][3] (or [V/2][3]).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Iterable, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import PREC, StagError, StagInfo, StagParams, StagProblem, check, lib
+
+__all__ = ["Lattice", "cg_solve_batch", "StagError", "solve_params"]
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _dev_tensor(t: torch.Tensor, name: str, shape_tail=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [..., {shape_tail}]")
+    return t
+
+
+def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, check_interval=16, max_restarts=5,
+                 profile=False, history_len=0, history=None, stall_window=10, stall_ratio=0.9) -> StagParams:
+    p = _lib.default_params()
+    p.tol = tol
+    p.prec = PREC[prec]
+    p.max_iter = max_iter
+    p.reliable_interval = reliable_interval
+    p.check_interval = check_interval
+    p.max_restarts = max_restarts
+    p.profile = 1 if profile else 0
+    p.history_len = history_len
+    if history is not None:
+        p.history = history.ctypes.data_as(C.POINTER(C.c_double))
+    p.stall_window = stall_window
+    p.stall_ratio = stall_ratio
+    return p
+
+
+class Lattice:
+    """A lattice of extents (Lx, Ly, Lz, Lt) on the current GPU, with packed links once loaded."""
+
+    def __init__(self, dims: Sequence[int], antiperiodic_t: bool = True):
+        self.dims = tuple(int(d) for d in dims)
+        h = C.c_void_p()
+        arr = (C.c_int32 * 4)(*self.dims)
+        check(lib().stag_create_lattice(arr, 1 if antiperiodic_t else 0, C.byref(h)), "stag_create_lattice")
+        self._h = h
+        self.half = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3] // 2
+        self._keep = []
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            check(lib().stag_destroy_lattice(self._h), "stag_destroy_lattice")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, name):
+        _dev_tensor(t, name, (self.half, 3))
+        nrhs = 1 if t.dim() == 2 else int(t.numel() // (self.half * 3))
+        return nrhs
+
+    def load_links(self, fat: torch.Tensor, lng: torch.Tensor | None = None, naik: float = -1.0 / 24.0,
+                   precs: Iterable[str] = ("f64",), stream=None):
+        Lx, Ly, Lz, Lt = self.dims
+        shape = (4, Lt, Lz, Ly, Lx, 3, 3)
+        _dev_tensor(fat, "fat")
+        if tuple(fat.shape) != shape:
+            raise ValueError(f"fat links must have shape {shape}")
+        if lng is not None:
+            _dev_tensor(lng, "lng")
+            if tuple(lng.shape) != shape:
+                raise ValueError(f"long links must have shape {shape}")
+        mask = 0
+        for p in precs:
+            mask |= 1 << PREC[p]
+        check(lib().stag_load_links(self._h, fat.data_ptr(), None if lng is None else lng.data_ptr(), float(naik),
+                                    mask, _stream(stream)), "stag_load_links")
+
+    def dslash(self, x: torch.Tensor, out_parity: int, prec: str = "f64", out=None, stream=None) -> torch.Tensor:
+        nrhs = self._vec(x, "in")
+        out = torch.empty_like(x) if out is None else out
+        self._vec(out, "out")
+        check(lib().stag_dslash(self._h, int(out_parity), x.data_ptr(), out.data_ptr(), nrhs, PREC[prec],
+                                _stream(stream)), "stag_dslash")
+        return out
+
+    def apply_m(self, x: torch.Tensor, mass, out=None, stream=None) -> torch.Tensor:
+        nrhs = self._vec(x, "in")
+        masses = [float(mass)] * nrhs if not isinstance(mass, (list, tuple)) else [float(m) for m in mass]
+        if len(masses) != nrhs:
+            raise ValueError("one mass per right-hand side")
+        out = torch.empty_like(x) if out is None else out
+        self._vec(out, "out")
+        m = (C.c_double * nrhs)(*masses)
+        check(lib().stag_apply_m(self._h, m, x.data_ptr(), out.data_ptr(), nrhs, _stream(stream)), "stag_apply_m")
+        return out
+
+    def cg_solve(self, b: torch.Tensor, mass, x0: torch.Tensor | None = None, raise_on_fail=True, stream=None,
+                 **params):
+        """Solve (4m^2 - D_eo D_oe) x = b; returns (x, [info dict per RHS])."""
+        nrhs = self._vec(b, "b")
+        masses = [float(mass)] * nrhs if not isinstance(mass, (list, tuple)) else [float(m) for m in mass]
+        if len(masses) != nrhs:
+            raise ValueError("one mass per right-hand side")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        prm = solve_params(**params)
+        infos = (StagInfo * nrhs)()
+        m = (C.c_double * nrhs)(*masses)
+        st = lib().stag_cg_solve(self._h, m, b.data_ptr(), x.data_ptr(), nrhs, C.byref(prm), infos, _stream(stream))
+        if raise_on_fail:
+            check(st, "stag_cg_solve")
+        return x, [i.as_dict() for i in infos]
+
+
+def cg_solve_batch(problems, raise_on_fail=True, stream=None, **params):
+    """problems: list of (Lattice, b, masses, x0 or None).  Returns ([x], [info dict per RHS in order])."""
+    n = len(problems)
+    arr = (StagProblem * n)()
+    xs, keep = [], []
+    total = 0
+    for i, (lat, b, masses, x0) in enumerate(problems):
+        nrhs = lat._vec(b, "b")
+        masses = [float(masses)] * nrhs if not isinstance(masses, (list, tuple)) else [float(m) for m in masses]
+        if len(masses) != nrhs:
+            raise ValueError("one mass per right-hand side")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        m = (C.c_double * nrhs)(*masses)
+        keep.append(m)
+        arr[i] = StagProblem(lat.handle, nrhs, C.cast(m, C.POINTER(C.c_double)), b.data_ptr(), x.data_ptr())
+        xs.append(x)
+        total += nrhs
+    prm = solve_params(**params)
+    infos = (StagInfo * total)()
+    st = lib().stag_cg_solve_batch(n, arr, C.byref(prm), infos, _stream(stream))
+    if raise_on_fail:
+        check(st, "stag_cg_solve_batch")
+    return xs, [i.as_dict() for i in infos]

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lowprec
+from oracle.cg import cg, true_residual
+from oracle.dslash import apply_m, dslash_at_sites, dslash_eo
+from stag_inputs import fat_field, gaussian_source, random_su3_field
+
+pytestmark = pytest.mark.gpu
+
+NAIK = -1.0 / 24.0
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make(dims, seed=5, naik=True, precs=("f64",), antiperiodic=True):
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    fat = fat_field(dims, seed)
+    lng = random_su3_field(dims, seed + 1) if naik else None
+    lat = Lattice(dims, antiperiodic)
+    lat.load_links(torch.from_numpy(fat).cuda(), None if lng is None else torch.from_numpy(lng).cuda(),
+                   NAIK, precs=precs)
+    return lat, fat, lng
+
+
+DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 8), (6, 6, 6, 6), (8, 8, 8, 8), (10, 4, 2, 6), (4, 2, 8, 2)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("nrhs", [1, 3, 4])
+def test_dslash_f64_matches_oracle(gpu_lib, dims, nrhs):
+    print(f"dslash f64 dims={dims} nrhs={nrhs}", flush=True)
+    lat, fat, lng = make(dims)
+    b = gaussian_source(dims, 11, nrhs)
+    x = torch.from_numpy(b).cuda()
+    for par in (0, 1):
+        out = lat.dslash(x, par).cpu().numpy()
+        for r in range(nrhs):
+            ref = dslash_eo(fat, lng, b[r], dims, par)
+            assert rel(out[r], ref) <= 1e-12, (par, r)
+
+
+@pytest.mark.parametrize("nrhs", [2, 8])
+def test_dslash_f64_multi_rhs_groups(gpu_lib, nrhs):
+    dims = (6, 4, 4, 6)
+    print(f"dslash f64 multi-rhs dims={dims} nrhs={nrhs}", flush=True)
+    lat, fat, lng = make(dims, seed=21)
+    b = gaussian_source(dims, 12, nrhs)
+    out = lat.dslash(torch.from_numpy(b).cuda(), 1).cpu().numpy()
+    for r in range(nrhs):
+        assert rel(out[r], dslash_eo(fat, lng, b[r], dims, 1)) <= 1e-12
+
+
+@pytest.mark.parametrize("antiperiodic", [True, False])
+def test_dslash_one_hop_and_periodic(gpu_lib, antiperiodic):
+    """No long links (the paper's Eq. (5) alone), both time boundary conditions."""
+    dims = (4, 6, 4, 8)
+    print(f"dslash one-hop antiperiodic={antiperiodic}", flush=True)
+    lat, fat, _ = make(dims, naik=False, antiperiodic=antiperiodic)
+    b = gaussian_source(dims, 13)[0]
+    out = lat.dslash(torch.from_numpy(b).cuda(), 0).cpu().numpy()
+    ref = dslash_eo(fat, None, b, dims, 0, antiperiodic_t=antiperiodic)
+    assert rel(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (2, 4, 6, 8)])
+def test_apply_m_matches_oracle(gpu_lib, dims):
+    print(f"apply_m dims={dims}", flush=True)
+    lat, fat, lng = make(dims)
+    b = gaussian_source(dims, 14, 2)
+    masses = [0.05, 0.3]
+    out = lat.apply_m(torch.from_numpy(b).cuda(), masses).cpu().numpy()
+    for r in range(2):
+        assert rel(out[r], apply_m(fat, lng, b[r], dims, masses[r])) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (2, 4, 6, 8)])
+def test_dslash_lowprec_within_bound(gpu_lib, prec, dims):
+    """Low-precision Dslash vs the oracle on identically rounded inputs, within a derived rounding bound.
+
+    FP32 arithmetic over 16 links x 3 colours (48 complex products, 4 FMAs each) is
+    bounded by gamma_200 ~ 200 u_32 sum |terms| per component; an FP16 output adds
+    half a binary16 spacing of the site scale, at most 2^-11 s.
+    """
+    print(f"dslash {prec} dims={dims}", flush=True)
+    lat, fat, lng = make(dims, precs=("f64", prec))
+    b = gaussian_source(dims, 15)[0]
+    u32 = 2.0 ** -24
+    for par in (0, 1):
+        out = lat.dslash(torch.from_numpy(b).cuda(), par, prec=prec).cpu().numpy()
+        mats, nbr = lowprec.site_matrices(fat, lng, dims, par)
+        mats_q = lowprec.round_matrices(mats, prec)
+        b_q = lowprec.round_spinor(b, prec)
+        ref = lowprec.apply_site_matrices(mats_q, nbr, b_q)
+        A = lowprec.abs_bound_terms(mats_q, nbr, b_q)
+        bound = 200 * u32 * A
+        if prec == "f16":
+            s = np.max(np.abs(np.stack([ref.real, ref.imag], -1)).reshape(len(ref), -1), axis=1)
+            bound = bound + (2.0 ** -11) * s[:, None] * 1.001
+        assert np.all(np.abs(out.real - ref.real) <= bound), (par, float((np.abs(out.real - ref.real) / bound).max()))
+        assert np.all(np.abs(out.imag - ref.imag) <= bound), par
+        # and the rounding actually happened: the result differs from the exact FP64 operator
+        assert rel(out, dslash_eo(fat, lng, b, dims, par)) > 1e-10
+
+
+def test_cg_f64_matches_oracle_iterates(gpu_lib):
+    """8^4, m = 0.05 (the small-lattice workload): GPU FP64 CG vs the oracle's Fig. 1 loop."""
+    dims = (8, 8, 8, 8)
+    print("cg f64 8^4", flush=True)
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    fat = random_su3_field(dims, 1001)  # unitary one-hop links for this workload
+    lng = random_su3_field(dims, 1002)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK)
+    m = 0.05
+    b = gaussian_source(dims, 1010)[0]
+    A = lambda v: apply_m(fat, lng, v, dims, m)
+    ref = cg(A, b, tol=1e-10, record=10)
+    hist = np.zeros((1, 10, 2))
+    x, info = lat.cg_solve(torch.from_numpy(b).cuda(), m, tol=1e-10, history_len=10, history=hist)
+    x = x.cpu().numpy()
+    assert info[0]["converged"] == 1
+    assert info[0]["true_resid"] <= 1e-10
+    assert true_residual(A, b, x) <= 1.05e-10
+    assert abs(info[0]["iters"] - ref.iters) <= max(5, 0.02 * ref.iters)
+    np.testing.assert_allclose(hist[0, :, 0], ref.alphas, rtol=1e-10)
+    np.testing.assert_allclose(hist[0, :, 1], ref.betas, rtol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_cg_mixed_precision_true_residual(gpu_lib, prec):
+    dims = (8, 8, 8, 8)
+    print(f"cg {prec} 8^4", flush=True)
+    lat, fat, lng = make(dims, seed=31, precs=("f64", prec))
+    m = 0.05
+    b = gaussian_source(dims, 32, 2)
+    x, info = lat.cg_solve(torch.from_numpy(b).cuda(), [m, 0.1], tol=1e-10, prec=prec, reliable_interval=50)
+    x = x.cpu().numpy()
+    for r, mr in enumerate([m, 0.1]):
+        assert info[r]["converged"] == 1 and info[r]["n_reliable"] >= 1
+        assert true_residual(lambda v: apply_m(fat, lng, v, dims, mr), b[r], x[r]) <= 1.05e-10
+
+
+def test_cg_batched_uneven_lattices(gpu_lib):
+    from paper_1010_4782_amd.stagcg import cg_solve_batch
+
+    print("cg batch uneven", flush=True)
+    probs, refs = [], []
+    for i, (dims, nrhs) in enumerate([((4, 4, 4, 4), 2), ((6, 4, 4, 6), 4), ((8, 8, 8, 8), 1)]):
+        lat, fat, lng = make(dims, seed=40 + i, precs=("f64", "f32"))
+        b = gaussian_source(dims, 50 + i, nrhs)
+        masses = [0.05 + 0.05 * r for r in range(nrhs)]
+        probs.append((lat, torch.from_numpy(b).cuda(), masses, None))
+        refs.append((fat, lng, dims, b, masses))
+    for prec in ("f64", "f32"):
+        xs, infos = cg_solve_batch(probs, tol=1e-10, prec=prec)
+        k = 0
+        for (fat, lng, dims, b, masses), x in zip(refs, xs):
+            x = x.cpu().numpy()
+            for r, mr in enumerate(masses):
+                assert infos[k]["converged"] == 1
+                assert true_residual(lambda v: apply_m(fat, lng, v, dims, mr), b[r], x[r]) <= 1.05e-10
+                k += 1
+
+
+def test_cg_edge_cases(gpu_lib):
+    from paper_1010_4782_amd._lib import STAG_ERR_NOT_CONVERGED, StagError
+
+    print("cg edge cases", flush=True)
+    dims = (4, 4, 4, 4)
+    lat, fat, lng = make(dims, seed=61)
+    b = gaussian_source(dims, 62, 2)
+    b[1] = 0.0                                   # zero source -> x = 0 exactly
+    bt = torch.from_numpy(b).cuda()
+    x, info = lat.cg_solve(bt, 0.1)
+    assert info[1]["iters"] == 0 and not x[1].abs().max().item()
+    # warm start at the solution: no iterations
+    x2, info2 = lat.cg_solve(bt[:1].contiguous(), 0.1, x0=x[:1].contiguous())
+    assert info2[0]["iters"] == 0 and info2[0]["converged"] == 1
+    # iteration cap reached: STAG_ERR_NOT_CONVERGED with a finite last iterate
+    x3, info3 = lat.cg_solve(bt[:1].contiguous(), 0.01, max_iter=3, max_restarts=0, raise_on_fail=False)
+    assert info3[0]["status"] == STAG_ERR_NOT_CONVERGED and info3[0]["iters"] == 3
+    assert torch.isfinite(x3).all()
+    with pytest.raises(StagError):
+        lat.cg_solve(bt[:1].contiguous(), 0.01, max_iter=3, max_restarts=0)
+
+
+def test_solves_are_deterministic(gpu_lib):
+    dims = (6, 6, 6, 6)
+    print("determinism", flush=True)
+    lat, _, _ = make(dims, seed=71)
+    bt = torch.from_numpy(gaussian_source(dims, 72)).cuda()
+    x1, i1 = lat.cg_solve(bt, 0.05)
+    x2, i2 = lat.cg_solve(bt, 0.05)
+    assert torch.equal(x1, x2) and i1[0]["iters"] == i2[0]["iters"]
+
+
+def test_argument_errors(gpu_lib):
+    from paper_1010_4782_amd._lib import StagError
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    with pytest.raises(StagError):
+        Lattice((3, 4, 4, 4))
+    lat = Lattice((4, 4, 4, 4))
+    v = torch.zeros(128, 3, dtype=torch.complex128, device="cuda")
+    with pytest.raises(StagError):
+        lat.dslash(v, 0)                        # links not loaded yet
+    lat2, _, _ = make((4, 4, 4, 4))
+    with pytest.raises(StagError):
+        lat2.dslash(v, 0, prec="f16")           # precision not packed
+
+
+def test_dslash_full_size_28cubed_96_sampled(gpu_lib):
+    """The paper-shaped lattice 28^3 x 96 in the launch shape the solver uses: sampled sites vs the oracle."""
+    dims = (28, 28, 28, 96)
+    print("dslash 28^3x96 sampled", flush=True)
+    fat = fat_field(dims, 2001)
+    lng = random_su3_field(dims, 2002)
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"))
+    b = gaussian_source(dims, 2010)[0]
+    rng = np.random.default_rng(3)
+    half = len(b)
+    sample = np.concatenate([rng.integers(0, half, 400), np.arange(64), np.arange(half - 64, half)])
+    for par in (0, 1):
+        out = lat.dslash(torch.from_numpy(b).cuda(), par).cpu().numpy()
+        ref = dslash_at_sites(fat, lng, b, dims, par, sample)
+        assert rel(out[sample], ref) <= 1e-12
