@@ -1,0 +1,188 @@
+"""Benchmark: time to a 1e-10 true residual on 28^3 x 96, mixed precision vs plain FP64 CG, plus Dslash GB/s.
+
+    python bench.py [--steps K] [--warmup W] [--workload 2] [--prec f16] [--no-cpu-baseline]
+
+A step is one pass of the whole hot path over the workload's synthetic input,
+which is resident in HBM before timing starts: pack the links (phases, signs and
+c_N folded; FP64 + the inner precision) and solve (4m^2 - D_eo D_oe) x = b with
+mixed-precision CG and FP64 reliable updates to true residual 1e-10.  The plain
+FP64 CG solve of the same system is timed once beside it.  Every Dslash launch of
+the timed steps is bracketed by HIP events on the solver's stream; their average
+duration gives the roofline figure.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 true residual vs plain FP64 CG; Dslash HBM GB/s (% of peak)"
+HBM_PEAK_GBPS = 8000.0
+# Compulsory bytes per output site and right-hand side of one Dslash launch:
+# 16 links + link scales + input and output colour vectors; the xpay launch of the
+# solver also reads d at the output site.  f16 colour vectors are 12 B of codes + a 4 B scale.
+LINK = {"f64": 144, "f32": 72, "f16": 36}
+LSCALE = {"f64": 0, "f32": 0, "f16": 8}
+VEC = {"f64": 48, "f32": 24, "f16": 16}
+FLOPS_PER_SITE = 1146
+
+
+def dslash_bytes_per_site(prec: str, xpay: bool = False) -> int:
+    return 16 * LINK[prec] + LSCALE[prec] + 2 * VEC[prec] + (VEC[prec] if xpay else 0)
+
+
+def host_info():
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model or platform.processor()}
+
+
+def cpu_baseline(fat, lng, b, dims, mass, iters_fp64):
+    """The oracle's CG as it stands, on one core, for a bounded sample: one Fig. 1 iteration
+    (plus the initial and final residual) on the full lattice, scaled to a whole solve."""
+    import numpy as np
+
+    from oracle.cg import cg
+    from oracle.dslash import apply_m
+
+    t0 = time.perf_counter()
+    cg(lambda v: apply_m(fat, lng, v, dims, mass), b, tol=1e-10, max_iter=1, max_restarts=0)
+    dt = time.perf_counter() - t0
+    per_iter = dt / 3.0   # three operator applications: r = b - A x, one iteration, the true residual
+    return {"value": per_iter * iters_fp64, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle CG iteration on {dims[0]}^3x{dims[3]} ({dt:.1f} s for 3 operator "
+                      f"applications), scaled by the GPU FP64 iteration count {iters_fp64}; extrapolated",
+            "per_iteration_s": per_iter}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--prec", default="f16", choices=["f32", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU runs are not supported.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1010_4782_amd.stagcg import Lattice
+    from stag_inputs import WORKLOADS, workload_links, workload_sources
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    w = WORKLOADS[a.workload]
+    dims, nrhs = w["lattices"][0]
+    mass = w["masses"][0]
+    tol = w["tol"]
+    t_gen = time.perf_counter()
+    fat, lng = workload_links(a.workload)
+    b = workload_sources(a.workload)
+    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    fat_d = torch.from_numpy(fat).to(dev)
+    lng_d = torch.from_numpy(lng).to(dev)
+    b_d = torch.from_numpy(b).to(dev)
+    lat = Lattice(dims)
+    half = lat.half
+    precs = ("f64", a.prec)
+    stream = torch.cuda.current_stream()
+
+    def step(prec, profile=True):
+        lat.load_links(fat_d, lng_d, -1.0 / 24.0, precs=precs)
+        x, info = lat.cg_solve(b_d, mass, tol=tol, prec=prec, reliable_interval=w.get("reliable_interval", 50),
+                               profile=profile)
+        return x, info[0]
+
+    for i in range(a.warmup):
+        step(a.prec)
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(a.steps):
+        x, info = step(a.prec)
+        infos.append(info)
+        print(f"# step {i}: {info['iters']} it, true resid {info['true_resid']:.3e}, {info['ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / a.steps
+
+    # Dslash roofline from the event-timed launches of the timed steps
+    d_ms = sum(i["dslash_ms"] for i in infos)
+    d_calls = sum(i["dslash_calls"] for i in infos)
+    avg_ms = d_ms / max(d_calls, 1)
+    bytes_per_launch = half * nrhs * (dslash_bytes_per_site(a.prec) + dslash_bytes_per_site(a.prec, True)) / 2.0
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC, "value": ms_per_step / 1e3, "unit": "s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "storage": a.prec, "data": "synthetic",
+        "config": {"workload": f"{dims[0]}^3x{dims[3]} single RHS, m={mass}, fat (0.6 SU(3) + noise) and "
+                               f"Naik links, true residual {tol}", "lattice": list(dims), "mass": mass,
+                   "tol": tol, "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every "
+                                         f"{w.get('reliable_interval', 50)}", "step": "load_links + solve"},
+        "mp_iters": infos[-1]["iters"], "mp_reliable_updates": infos[-1]["n_reliable"],
+        "mp_true_resid": infos[-1]["true_resid"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": f"k_dslash<{a.prec}> (plain and xpay launches)",
+                     "avg_launch_us": avg_ms * 1e3, "launches": d_calls,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not a.no_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x64, i64 = step("f64")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        avg64 = i64["dslash_ms"] / max(i64["dslash_calls"], 1)
+        bpl64 = half * nrhs * (dslash_bytes_per_site("f64") + dslash_bytes_per_site("f64", True)) / 2.0
+        gbs64 = bpl64 / (avg64 * 1e-3) / 1e9
+        out["fp64_cg_s"] = t64
+        out["fp64_iters"] = i64["iters"]
+        out["fp64_true_resid"] = i64["true_resid"]
+        out["speedup_vs_fp64_cg"] = t64 / (ms_per_step / 1e3)
+        out["dslash_f64"] = {"GBps": gbs64, "frac_of_hbm_peak": gbs64 / HBM_PEAK_GBPS, "avg_launch_us": avg64 * 1e3,
+                             "gflops": half * nrhs * FLOPS_PER_SITE / (avg64 * 1e-3) / 1e9}
+        print(f"# fp64 CG: {i64['iters']} it, {t64:.3f} s, Dslash {gbs64:.0f} GB/s", file=sys.stderr, flush=True)
+        del x64
+    out["dslash_" + a.prec] = {"GBps": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBPS,
+                               "avg_launch_us": avg_ms * 1e3,
+                               "gflops": half * nrhs * FLOPS_PER_SITE / (avg_ms * 1e-3) / 1e9}
+    if not a.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        iters = out.get("fp64_iters", infos[-1]["iters"])
+        cb = cpu_baseline(fat, lng, b[0], dims, mass, iters)
+        cb["host"] = host_info()
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

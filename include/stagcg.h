@@ -68,7 +68,10 @@ typedef struct {
   double tol;                /* target true residual ||b - M x|| / ||b|| (default 1e-10) */
   int32_t max_iter;          /* inner iterations per restart; <= 0: 3V/2 (the dimension N_dim of Fig. 1) */
   int32_t prec;              /* stag_prec of the inner iteration; STAG_F64 = plain CG of Fig. 1 */
-  int32_t reliable_interval; /* mixed precision: iterations between FP64 residual recomputations (default 50) */
+  int32_t reliable_interval; /* mixed precision: at most this many iterations between FP64 residual
+                                recomputations ("reliable updates", default 50) */
+  double reliable_delta;     /* mixed precision: also update once ||r|| fell below reliable_delta times its value
+                                at the previous update (default 0.1; <= 0 disables this trigger) */
   int32_t check_interval;    /* iterations between host convergence polls (default 16) */
   int32_t max_restarts;      /* true-residual restarts after the iterated residual converged (default 5) */
   int32_t precond;           /* stag_precond */

@@ -32,6 +32,7 @@ class StagParams(C.Structure):
         ("max_iter", C.c_int32),
         ("prec", C.c_int32),
         ("reliable_interval", C.c_int32),
+        ("reliable_delta", C.c_double),
         ("check_interval", C.c_int32),
         ("max_restarts", C.c_int32),
         ("precond", C.c_int32),

@@ -161,19 +161,66 @@ __global__ __launch_bounds__(kMaxWG) void k_zero(Batch B, int v_id, int gate) {
   store_spinor<P>(vec_ptr<P>(m, v_id), m.cb, z);
 }
 
+// partial[0,1,2] = Re <r, d>, Im <r, d>, |r|^2 with r the low-precision residual.
+template <int P>
+__global__ __launch_bounds__(kMaxWG) void k_rd_dot(Batch B, int gate) {
+  __shared__ double lds[12];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate)) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (m.live) {
+    Cx<typename RealOf<P>::T> r[3], d[3];
+    load_spinor<P>(vec_ptr<P>(m, V_RL), m.cb, r);
+    load_spinor<P>(vec_ptr<P>(m, V_D), m.cb, d);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s[0] += (double)r[c].re * d[c].re + (double)r[c].im * d[c].im;
+      s[1] += (double)r[c].re * d[c].im - (double)r[c].im * d[c].re;
+      s[2] += (double)r[c].re * r[c].re + (double)r[c].im * r[c].im;
+    }
+  }
+  block_sum<3>(s, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) B.partial[((long)m.slot * kPartialSlots + k) * B.pstride + m.tile] = s[k];
+}
+
+// d += c r with c = 1 - <r, d>/|r|^2 (from FIN_ORTHO): afterwards <r, d> = |r|^2 as in exact CG.
+template <int P>
+__global__ __launch_bounds__(kMaxWG) void k_d_fix(Batch B, int gate) {
+  using T = typename RealOf<P>::T;
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate) || !m.live) return;
+  const T cr = (T)B.scal[m.slot].cre, ci = (T)B.scal[m.slot].cim;
+  Cx<T> r[3], d[3];
+  char* dp = vec_ptr<P>(m, V_D);
+  load_spinor<P>(vec_ptr<P>(m, V_RL), m.cb, r);
+  load_spinor<P>(dp, m.cb, d);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    d[c].re += cr * r[c].re - ci * r[c].im;
+    d[c].im += cr * r[c].im + ci * r[c].re;
+  }
+  store_spinor<P>(dp, m.cb, d);
+}
+
 // One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.
 __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
                                                   double* hist, int hist_stride) {
-  __shared__ double lds[4];
+  __shared__ double lds[12];
   const int slot = blockIdx.x;
   int p = 0;
   while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
   if (!slot_on(B.scal, slot, gate)) return;
   const int ntiles = ceil_div(B.probs[p].g.half, producer_wg);
-  const double* src = B.partial + ((long)slot * kPartialSlots + kind) * B.pstride;
-  double s[1] = {0.0};
-  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s[0] += src[i];
-  block_sum<1>(s, lds);
+  const int nk = what == FIN_ORTHO ? 3 : 1;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < nk; ++k) {
+    const double* src = B.partial + ((long)slot * kPartialSlots + kind + k) * B.pstride;
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s[k] += src[i];
+  }
+  block_sum<3>(s, lds);
   if (threadIdx.x != 0) return;
   const double sum = s[0];
   Scal& sc = B.scal[slot];
@@ -221,6 +268,10 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
       if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2 + 1] = sc.beta;
       sc.iter += 1;
       if (sum <= sc.thr) sc.state = 1;
+      if (sum <= sc.rel_thr) {
+        sc.state = 1;
+        sc.flags |= kFlagRelDue;
+      }
       if (sc.iter >= sc.max_iter) {
         sc.state = 1;
         sc.flags |= kFlagMaxIter;
@@ -233,6 +284,18 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
     case FIN_RELIABLE:
       sc.delta = sum;
       break;
+    case FIN_ORTHO: {
+      const double n2 = s[2];
+      if (n2 > 0.0 && isfinite(n2)) {
+        sc.cre = 1.0 - sum / n2;
+        sc.cim = -s[1] / n2;
+      } else {
+        sc.cre = 0.0;
+        sc.cim = 0.0;
+      }
+      sc.delta = n2;
+      break;
+    }
   }
 }
 
@@ -291,6 +354,22 @@ hipError_t launch_copy_vec(const BatchHost& bh, int src_prec, int src_id, int ds
   STAG_COPY(P32, P64) STAG_COPY(P16, P64)
 #undef STAG_COPY
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_rd_dot(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  STAG_PREC_SWITCH(prec, k_rd_dot, B, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  STAG_PREC_SWITCH(prec, k_d_fix, B, gate);
+  return hipGetLastError();
 }
 
 hipError_t launch_add_lo_to_hi(const BatchHost& bh, int gate, int wg, hipStream_t st) {

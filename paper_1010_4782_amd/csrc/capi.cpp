@@ -205,6 +205,7 @@ void stag_cg_params_default(stag_cg_params* prm) {
   prm->max_iter = 0;
   prm->prec = STAG_F64;
   prm->reliable_interval = 50;
+  prm->reliable_delta = 0.1;
   prm->check_interval = 16;
   prm->max_restarts = 5;
   prm->precond = STAG_PRECOND_NONE;

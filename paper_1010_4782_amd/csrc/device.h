@@ -225,11 +225,16 @@ __device__ __forceinline__ int find_problem(const Batch& B, int bid) {
 }
 
 // gate: 0 = every slot not finished (state <= 2), 1 = running (state 0),
-//       2 = running or pending x update (state <= 1), 3 = every slot
+//       2 = running or pending x update (state <= 1), 3 = every slot, 4 = state 1 only
 __device__ __forceinline__ bool slot_on(const Scal* scal, int slot, int gate) {
   if (gate == 3) return true;
   const int st = scal[slot].state;
-  return gate == 1 ? st == 0 : (gate == 2 ? st <= 1 : st <= 2);
+  switch (gate) {
+    case 1: return st == 0;
+    case 2: return st <= 1;
+    case 4: return st == 1;
+    default: return st <= 2;
+  }
 }
 
 }  // namespace stag

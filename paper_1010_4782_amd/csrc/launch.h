@@ -55,8 +55,12 @@ enum Fin : int {
   FIN_ALPHA = 2,     // state 1 -> 2 ; else alpha = delta / dAd (breakdown -> NaN flag, state 2)
   FIN_BETA = 3,      // delta_old = delta ; delta = sum ; beta ; iter++ ; stop test
   FIN_TRUE = 4,      // aux = sqrt(sum / b2) (true residual)
-  FIN_RELIABLE = 5   // delta = sum (after the FP64 residual recomputation)
+  FIN_RELIABLE = 5,  // delta = sum (after the FP64 residual recomputation)
+  FIN_ORTHO = 6      // kinds 0,1,2 = Re<r,d>, Im<r,d>, |r|^2: c = 1 - <r,d>/|r|^2 ; delta = |r|^2
 };
+// Mixed precision, after a reliable update: restore <d, r> = |r|^2 for the new residual r.
+hipError_t launch_rd_dot(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);
+hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);
 
 // Packing and conversions.
 hipError_t launch_pack_links(int prec, const void* fat, const void* lng, double naik, const Geo& g, int antiper,

@@ -260,6 +260,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
         sc.state = 0;
         sc.iter = 0;
         sc.flags = 0;
+        sc.rel_thr = (mixed && prm.reliable_delta > 0.0) ? prm.reliable_delta * prm.reliable_delta * sc.delta : 0.0;
         passes[s] += 1;
         any_run = true;
       }
@@ -281,38 +282,64 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
       STAG_HIP_TRY(launch_copy_vec(R.bh, P, V_RL, P, V_D, 1, kVecWG, st));
       STAG_HIP_TRY(launch_zero_vec(R.bh, P32, V_XL, 1, kVecWG, st));
       int since = 0;
+      std::vector<char> parked(nslots, 0);
+      const double drop2 = prm.reliable_delta > 0.0 ? prm.reliable_delta * prm.reliable_delta : 0.0;
       for (;;) {
         for (int i = 0; i < prm.check_interval; ++i) STAG_HIP_TRY(iteration(R, x_prec, x_id, d_hist));
         since += prm.check_interval;
         STAG_HIP_TRY(pull_scal(R, "poll-mp"));
-        bool running = false;
-        for (int s = 0; s < nslots; ++s) running |= R.h_scal[s].state == 0;
-        if (running && since < prm.reliable_interval) continue;
-        // reliable update for running or just-stopped slots: x += x_lo, r = b - M x in FP64, r_lo = r.
-        // A slot that stopped early in the last batch of iterations has moved on to state 2; bring it
-        // back to 1 (unless it broke down) so that the update covers it.
-        since = 0;
+        // Slots that stopped (apparent convergence, residual drop, iteration cap) wait for a
+        // reliable update; once reliable_interval iterations have passed, every running slot does.
+        bool any_wait = false, running = false;
         for (int s = 0; s < nslots; ++s) {
           Scal& sc = R.h_scal[s];
-          if (sc.state == 2 && !(sc.flags & kFlagNaN)) sc.state = 1;
+          if ((sc.state == 1 || sc.state == 2) && !(sc.flags & kFlagNaN)) {
+            sc.state = 1;
+            any_wait = true;
+          }
+          running |= sc.state == 0;
+        }
+        if (!running && !any_wait) {  // everything parked or broken down
+          for (int s = 0; s < nslots; ++s)
+            if (parked[s]) R.h_scal[s].state = 2;
+          STAG_HIP_TRY(push_scal(R));
+          break;
+        }
+        const bool interval_due = since >= prm.reliable_interval;
+        if (!any_wait && !interval_due) continue;
+        if (interval_due) {
+          for (int s = 0; s < nslots; ++s)
+            if (R.h_scal[s].state == 0) R.h_scal[s].state = 1;
+          since = 0;
         }
         STAG_HIP_TRY(push_scal(R));
-        STAG_HIP_TRY(launch_add_lo_to_hi(R.bh, 2, kVecWG, st));
-        STAG_HIP_TRY(true_residual(R, 2));
-        STAG_HIP_TRY(launch_copy_vec(R.bh, P64, V_R, P, V_RL, 2, kVecWG, st));
+        // reliable update (slots in state 1): x += x_lo, r = b - M x in FP64, r_lo = r, and
+        // restore <d, r> = |r|^2 for the new residual.
+        STAG_HIP_TRY(launch_add_lo_to_hi(R.bh, 4, kVecWG, st));
+        STAG_HIP_TRY(true_residual(R, 4));
+        STAG_HIP_TRY(launch_copy_vec(R.bh, P64, V_R, P, V_RL, 4, kVecWG, st));
+        STAG_HIP_TRY(launch_rd_dot(R.bh, P, 4, kVecWG, st));
+        STAG_HIP_TRY(launch_finalize(R.bh, FIN_ORTHO, 0, 4, kVecWG, nullptr, 0, st));
+        STAG_HIP_TRY(launch_d_fix(R.bh, P, 4, kVecWG, st));
         STAG_HIP_TRY(pull_scal(R, "reliable"));
-        bool cont = false;
+        bool cont = running;
         for (int s = 0; s < nslots; ++s) {
           Scal& sc = R.h_scal[s];
-          if (sc.state > 1) continue;
+          if (sc.state != 1) continue;
           n_rel[s] += 1;
+          sc.flags &= ~kFlagRelDue;
           if (sc.aux <= prm.tol || (sc.flags & kFlagMaxIter)) {
-            sc.state = 2;  // the outer loop classifies it
+            sc.state = 3;  // out of the inner loop; the outer loop classifies it
+            parked[s] = 1;
           } else {
             sc.state = 0;
+            sc.rel_thr = drop2 * sc.delta;
             cont = true;
           }
         }
+        if (!cont)
+          for (int s = 0; s < nslots; ++s)
+            if (parked[s]) R.h_scal[s].state = 2;
         STAG_HIP_TRY(push_scal(R));
         if (!cont) break;
       }

@@ -10,7 +10,7 @@ constexpr int kWave = 64;        // gfx950 wavefront
 constexpr int kMaxWG = 256;      // largest workgroup any kernel is launched with
 constexpr int kLinks = 16;       // packed matrices per output site: 4 directions x {fat fwd, fat bwd, long fwd, long bwd}
 constexpr int kMaxProb = 16;     // problems per batched launch
-constexpr int kPartialSlots = 2; // reduction partials per slot kept apart (dot and norm)
+constexpr int kPartialSlots = 3; // reduction partials per slot kept apart (up to three sums)
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
 
@@ -44,6 +44,8 @@ struct Scal {
   double rz;         // FCG: <z, r>
   double rz_new;     // FCG
   double aux;        // scratch scalar (true residual, stall monitor)
+  double rel_thr;    // mixed precision: r^dag r below which a reliable update is due
+  double cre, cim;   // mixed precision: d += (cre + i cim) r after a reliable update
   int state;
   int iter;          // iterations since the last (re)start
   int max_iter;
@@ -53,7 +55,7 @@ struct Scal {
 };
 static_assert(sizeof(Scal) % 8 == 0, "Scal alignment");
 
-enum ScalFlags : int { kFlagNaN = 1, kFlagMaxIter = 2 };
+enum ScalFlags : int { kFlagNaN = 1, kFlagMaxIter = 2, kFlagRelDue = 4 };
 
 // Vector roles in a solver workspace (one [nrhs][V/2][3] array per role and problem).
 enum VecId : int {

@@ -36,13 +36,15 @@ def _dev_tensor(t: torch.Tensor, name: str, shape_tail=None) -> torch.Tensor:
     return t
 
 
-def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, check_interval=16, max_restarts=5,
-                 profile=False, history_len=0, history=None, stall_window=10, stall_ratio=0.9) -> StagParams:
+def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliable_delta=0.1, check_interval=16,
+                 max_restarts=5, profile=False, history_len=0, history=None, stall_window=10,
+                 stall_ratio=0.9) -> StagParams:
     p = _lib.default_params()
     p.tol = tol
     p.prec = PREC[prec]
     p.max_iter = max_iter
     p.reliable_interval = reliable_interval
+    p.reliable_delta = reliable_delta
     p.check_interval = check_interval
     p.max_restarts = max_restarts
     p.profile = 1 if profile else 0
