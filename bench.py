@@ -68,6 +68,38 @@ def cpu_baseline(fat, lng, b, dims, mass, iters_fp64):
             "per_iteration_s": per_iter}
 
 
+def copy_ceiling(torch, nbytes=2 << 30, reps=10):
+    """Device-to-device copy of a 2 GiB buffer: the streaming ceiling on this GPU (read + write bytes / time)."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del src, dst
+    return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes,
+            "avg_launch_us": ms * 1e3}
+
+
+def measured_traffic(prec: str, dims):
+    """HBM bytes per Dslash launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source and this workload; otherwise None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +109,8 @@ def main(argv=None):
     ap.add_argument("--prec", default="f16", choices=["f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="cap the inner iterations (for counter-collection runs; the solve then stops early)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU runs are not supported.",
@@ -113,7 +147,8 @@ def main(argv=None):
     def step(prec, profile=True):
         lat.load_links(fat_d, lng_d, -1.0 / 24.0, precs=precs)
         x, info = lat.cg_solve(b_d, mass, tol=tol, prec=prec, reliable_interval=w.get("reliable_interval", 50),
-                               profile=profile)
+                               profile=profile, max_iter=a.max_iter, max_restarts=0 if a.max_iter else 5,
+                               raise_on_fail=a.max_iter == 0)
         return x, info[0]
 
     for i in range(a.warmup):
@@ -149,7 +184,7 @@ def main(argv=None):
         "mp_iters": infos[-1]["iters"], "mp_reliable_updates": infos[-1]["n_reliable"],
         "mp_true_resid": infos[-1]["true_resid"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(a.prec, dims),
                      "kernel": f"k_dslash<{a.prec}> (plain and xpay launches)",
                      "avg_launch_us": avg_ms * 1e3, "launches": d_calls,
                      "bytes_per_launch": bytes_per_launch},
@@ -174,6 +209,7 @@ def main(argv=None):
     out["dslash_" + a.prec] = {"GBps": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBPS,
                                "avg_launch_us": avg_ms * 1e3,
                                "gflops": half * nrhs * FLOPS_PER_SITE / (avg_ms * 1e-3) / 1e9}
+    out["copy_ceiling"] = copy_ceiling(torch)
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         iters = out.get("fp64_iters", infos[-1]["iters"])

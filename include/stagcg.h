@@ -94,8 +94,9 @@ typedef struct {
   int32_t status;            /* stag_status of this right-hand side */
   double true_resid;         /* ||b - M x|| / ||b|| of the returned x, computed in FP64 on the GPU */
   double ms;                 /* wall time of the whole call (same for every RHS of a call) */
-  double dslash_ms;          /* profile=1: summed duration of the Dslash launches of the call */
-  int32_t dslash_calls;      /* profile=1: number of Dslash launches timed */
+  double dslash_ms;          /* profile=1: summed duration of the inner-iteration Dslash launches that did
+                                work (launches whose right-hand sides had all stopped are left out) */
+  int32_t dslash_calls;      /* profile=1: number of those launches */
   int32_t dslash_prec;       /* precision of the timed Dslash launches (inner iteration precision) */
   double dslash_sites;       /* profile=1: output sites x RHS processed per timed launch, averaged */
 } stag_cg_info;

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and rejects bad
+arguments before touching the GPU (these calls return before any HIP call, so they run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stagcg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stag_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1010_4782_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libstagcg.so is not built: run python -m paper_1010_4782_amd.build")
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("stag_create_lattice", "stag_load_links", "stag_dslash", "stag_cg_solve"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1010_4782_amd import _lib
+
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"{name} has no ctypes signature"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+
+    from paper_1010_4782_amd import _lib
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler on this host")
+    mirrors = {"stag_cg_params": _lib.StagParams, "stag_cg_info": _lib.StagInfo, "stag_problem": _lib.StagProblem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "stagcg.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert int(got[f"{cname}.{field}"]) == getattr(py, field).offset, f"{cname}.{field}"
+
+
+def test_params_default(lib):
+    from paper_1010_4782_amd import _lib
+
+    p = _lib.default_params()
+    assert p.tol == 1e-10 and p.reliable_interval == 50 and p.reliable_delta == 0.1
+    assert p.check_interval == 16 and p.max_restarts == 5 and p.prec == 0
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, -2, 4), (4, 4, 4, 5)])
+def test_create_lattice_rejects_bad_dims(lib, dims):
+    h = C.c_void_p()
+    st = lib.stag_create_lattice((C.c_int32 * 4)(*dims), 1, C.byref(h))
+    assert st == 1 and not h.value
+    assert b"even" in lib.stag_last_error()
+
+
+def test_create_lattice_rejects_huge_volume(lib):
+    h = C.c_void_p()
+    assert lib.stag_create_lattice((C.c_int32 * 4)(2048, 2048, 512, 2), 1, C.byref(h)) == 1
+
+
+def test_null_arguments_are_rejected(lib):
+    assert lib.stag_create_lattice(None, 1, None) == 1
+    assert lib.stag_destroy_lattice(None) == 1
+    assert lib.stag_load_links(None, None, None, -1 / 24, 1, None) == 1
+    assert lib.stag_dslash(None, 0, None, None, 1, 0, None) == 1
+    assert lib.stag_apply_m(None, None, None, None, 1, None) == 1
+    assert lib.stag_lattice_info(None, None, None) == 1
+
+
+def test_batch_argument_validation(lib):
+    from paper_1010_4782_amd import _lib
+
+    info = (_lib.StagInfo * 1)()
+    prm = _lib.default_params()
+    assert lib.stag_cg_solve_batch(0, None, C.byref(prm), info, None) == 1
+    assert lib.stag_cg_solve_batch(17, None, C.byref(prm), info, None) == 1
+    probs = (_lib.StagProblem * 1)()
+    assert lib.stag_cg_solve_batch(1, probs, C.byref(prm), info, None) == 1      # NULL lattice
+    prm.tol = -1.0
+    assert lib.stag_cg_solve_batch(1, probs, C.byref(prm), info, None) == 1
+    assert b"tol" in lib.stag_last_error()
