@@ -120,100 +120,121 @@ def main(argv=None):
     import numpy as np
     import torch
 
-    from paper_1010_4782_amd.stagcg import Lattice
+    from paper_1010_4782_amd.stagcg import Lattice, cg_solve_batch
     from stag_inputs import WORKLOADS, workload_links, workload_sources
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     w = WORKLOADS[a.workload]
-    dims, nrhs = w["lattices"][0]
-    mass = w["masses"][0]
     tol = w["tol"]
+    rel_int = w.get("reliable_interval", 50)
     t_gen = time.perf_counter()
-    fat, lng = workload_links(a.workload)
-    b = workload_sources(a.workload)
-    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-
     dev = torch.device("cuda:0")
-    fat_d = torch.from_numpy(fat).to(dev)
-    lng_d = torch.from_numpy(lng).to(dev)
-    b_d = torch.from_numpy(b).to(dev)
-    lat = Lattice(dims)
-    half = lat.half
+    host, probs = [], []
+    for li, (dims, nrhs) in enumerate(w["lattices"]):
+        fat, lng = workload_links(a.workload, li)
+        b = workload_sources(a.workload, li)
+        lat = Lattice(dims)
+        probs.append(dict(lat=lat, dims=dims, nrhs=nrhs, fat=torch.from_numpy(fat).to(dev),
+                          lng=torch.from_numpy(lng).to(dev), b=torch.from_numpy(b).to(dev)))
+        host.append((fat, lng, b))
+        if a.workload != 2:
+            del fat, lng
+            host[-1] = None
+    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    masses = w["masses"]
     precs = ("f64", a.prec)
-    stream = torch.cuda.current_stream()
 
     def step(prec, profile=True):
-        lat.load_links(fat_d, lng_d, -1.0 / 24.0, precs=precs)
-        x, info = lat.cg_solve(b_d, mass, tol=tol, prec=prec, reliable_interval=w.get("reliable_interval", 50),
-                               profile=profile, max_iter=a.max_iter, max_restarts=0 if a.max_iter else 5,
-                               raise_on_fail=a.max_iter == 0)
-        return x, info[0]
+        """load_links on every lattice, then one batched solve per mass; returns the infos."""
+        for p in probs:
+            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs)
+        infos = []
+        for m in masses:
+            batch = [(p["lat"], p["b"], [m] * p["nrhs"], None) for p in probs]
+            xs, inf = cg_solve_batch(batch, tol=tol, prec=prec, reliable_interval=rel_int, profile=profile,
+                                     max_iter=a.max_iter, max_restarts=0 if a.max_iter else 5,
+                                     raise_on_fail=a.max_iter == 0, autotune=True)
+            infos.append(inf)
+        return infos
+
+    def dslash_rate(infos, prec):
+        """Algorithmic GB/s of the inner-iteration Dslash launches (plain and xpay averaged)."""
+        ms = sum(i[0]["dslash_ms"] for i in infos)
+        calls = sum(i[0]["dslash_calls"] for i in infos)
+        r = infos[0][0]["dslash_rhs"]
+        per_launch = 0.0
+        for p in probs:
+            groups = p["nrhs"] // r
+            site = 16 * LINK[prec] + LSCALE[prec] + r * (2 * VEC[prec]) + r * VEC[prec] / 2.0
+            per_launch += p["lat"].half * groups * site
+        avg = ms / max(calls, 1)
+        sites = sum(p["lat"].half * p["nrhs"] for p in probs)
+        return per_launch / (avg * 1e-3) / 1e9, avg, per_launch, calls, sites * FLOPS_PER_SITE / (avg * 1e-3) / 1e9
 
     for i in range(a.warmup):
         step(a.prec)
         print(f"# warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    all_infos = []
     for i in range(a.steps):
-        x, info = step(a.prec)
-        infos.append(info)
-        print(f"# step {i}: {info['iters']} it, true resid {info['true_resid']:.3e}, {info['ms']:.1f} ms",
-              file=sys.stderr, flush=True)
+        infos = step(a.prec)
+        all_infos.append(infos)
+        its = [max(x["iters"] for x in inf) for inf in infos]
+        res = max(x["true_resid"] for inf in infos for x in inf)
+        print(f"# step {i}: max iterations per batch {its}, worst true resid {res:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / a.steps
-
-    # Dslash roofline from the event-timed launches of the timed steps
-    d_ms = sum(i["dslash_ms"] for i in infos)
-    d_calls = sum(i["dslash_calls"] for i in infos)
-    avg_ms = d_ms / max(d_calls, 1)
-    bytes_per_launch = half * nrhs * (dslash_bytes_per_site(a.prec) + dslash_bytes_per_site(a.prec, True)) / 2.0
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-
+    flat = [inf for infos in all_infos for inf in infos]
+    achieved, avg_ms, bytes_per_launch, d_calls, gflops = dslash_rate(flat, a.prec)
+    last = all_infos[-1]
+    d0 = probs[0]["dims"]
+    shape = "+".join(f"{p['dims'][0]}^3x{p['dims'][3]}x{p['nrhs']}" if p["dims"][0] == p["dims"][2] else
+                     f"{'x'.join(map(str, p['dims']))}x{p['nrhs']}" for p in probs)
     out = {
         "metric": METRIC, "value": ms_per_step / 1e3, "unit": "s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "storage": a.prec, "data": "synthetic",
-        "config": {"workload": f"{dims[0]}^3x{dims[3]} single RHS, m={mass}, fat (0.6 SU(3) + noise) and "
-                               f"Naik links, true residual {tol}", "lattice": list(dims), "mass": mass,
-                   "tol": tol, "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every "
-                                         f"{w.get('reliable_interval', 50)}", "step": "load_links + solve"},
-        "mp_iters": infos[-1]["iters"], "mp_reliable_updates": infos[-1]["n_reliable"],
-        "mp_true_resid": infos[-1]["true_resid"],
+        "config": {"workload": f"{shape} (lattice x RHS), m={masses}, fat (0.6 SU(3) + noise) and Naik links, "
+                               f"true residual {tol}", "lattices": [list(p["dims"]) for p in probs],
+                   "nrhs": [p["nrhs"] for p in probs], "masses": masses, "tol": tol,
+                   "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every {rel_int} "
+                             f"iterations or after a 10x residual drop", "step": "load_links + solve"},
+        "mp_iters": [max(x["iters"] for x in inf) for inf in last],
+        "mp_reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
+        "mp_true_resid": max(x["true_resid"] for inf in last for x in inf),
+        "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(a.prec, dims),
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(a.prec, d0) if len(probs) == 1 and probs[0]["nrhs"] == 1 else None,
                      "kernel": f"k_dslash<{a.prec}> (plain and xpay launches)",
-                     "avg_launch_us": avg_ms * 1e3, "launches": d_calls,
-                     "bytes_per_launch": bytes_per_launch},
+                     "avg_launch_us": avg_ms * 1e3, "launches": d_calls, "bytes_per_launch": bytes_per_launch},
     }
     if not a.no_fp64:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x64, i64 = step("f64")
+        i64 = step("f64")
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
-        avg64 = i64["dslash_ms"] / max(i64["dslash_calls"], 1)
-        bpl64 = half * nrhs * (dslash_bytes_per_site("f64") + dslash_bytes_per_site("f64", True)) / 2.0
-        gbs64 = bpl64 / (avg64 * 1e-3) / 1e9
+        gbs64, avg64, _, _, gf64 = dslash_rate(i64, "f64")
         out["fp64_cg_s"] = t64
-        out["fp64_iters"] = i64["iters"]
-        out["fp64_true_resid"] = i64["true_resid"]
+        out["fp64_iters"] = [max(x["iters"] for x in inf) for inf in i64]
+        out["fp64_true_resid"] = max(x["true_resid"] for inf in i64 for x in inf)
         out["speedup_vs_fp64_cg"] = t64 / (ms_per_step / 1e3)
         out["dslash_f64"] = {"GBps": gbs64, "frac_of_hbm_peak": gbs64 / HBM_PEAK_GBPS, "avg_launch_us": avg64 * 1e3,
-                             "gflops": half * nrhs * FLOPS_PER_SITE / (avg64 * 1e-3) / 1e9}
-        print(f"# fp64 CG: {i64['iters']} it, {t64:.3f} s, Dslash {gbs64:.0f} GB/s", file=sys.stderr, flush=True)
-        del x64
+                             "gflops": gf64}
+        print(f"# fp64 CG: {out['fp64_iters']} it, {t64:.3f} s, Dslash {gbs64:.0f} GB/s", file=sys.stderr, flush=True)
     out["dslash_" + a.prec] = {"GBps": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBPS,
-                               "avg_launch_us": avg_ms * 1e3,
-                               "gflops": half * nrhs * FLOPS_PER_SITE / (avg_ms * 1e-3) / 1e9}
+                               "avg_launch_us": avg_ms * 1e3, "gflops": gflops}
     out["copy_ceiling"] = copy_ceiling(torch)
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.workload == 2:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        iters = out.get("fp64_iters", infos[-1]["iters"])
-        cb = cpu_baseline(fat, lng, b[0], dims, mass, iters)
+        iters = out.get("fp64_iters", out["mp_iters"])[0]
+        fat, lng, b = host[0]
+        cb = cpu_baseline(fat, lng, b[0], probs[0]["dims"], masses[0], iters)
         cb["host"] = host_info()
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

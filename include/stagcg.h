@@ -81,7 +81,8 @@ typedef struct {
   int32_t profile;           /* 1: time every Dslash launch with HIP events (stag_cg_info.dslash_ms) */
   int32_t history_len;       /* record the first history_len (alpha, beta) pairs per RHS into history */
   double* history;           /* host [nrhs][history_len][2] or NULL */
-  int32_t reserved[8];
+  int32_t autotune;          /* 1: time the Dslash launch shapes on first use of a (lattices, nrhs, prec) key */
+  int32_t reserved[7];
 } stag_cg_params;
 
 /* Per right-hand side result of a solve. */
@@ -99,7 +100,16 @@ typedef struct {
   int32_t dslash_calls;      /* profile=1: number of those launches */
   int32_t dslash_prec;       /* precision of the timed Dslash launches (inner iteration precision) */
   double dslash_sites;       /* profile=1: output sites x RHS processed per timed launch, averaged */
+  int32_t dslash_wg;         /* launch shape used by the inner-iteration Dslash: sites per workgroup */
+  int32_t dslash_rhs;        /* ... and right-hand sides per lane */
 } stag_cg_info;
+
+/* A Dslash launch shape and its measured time. */
+typedef struct {
+  int32_t wg;                /* output sites per workgroup: 64, 128 or 256 */
+  int32_t rhs_per_lane;      /* right-hand sides each lane applies a loaded link to: 1, 2, 4 or 8 */
+  double us;                 /* average launch time (stag_tune_dslash), 0 if not timed */
+} stag_shape;
 
 /* One problem of a batched solve: a lattice with its own right-hand sides and masses. */
 typedef struct {
@@ -160,6 +170,19 @@ stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b,
  * all problems.  probs: host [nprob]; info: host [sum of nrhs], in problem order. */
 stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const stag_cg_params* prm,
                                 stag_cg_info* info, void* stream);
+
+/* Autotuner of the Dslash launch shape (multi-right-hand-side batching, Sec. 3.4's occupancy tuning
+ * done by measurement).  stag_tune_dslash times every candidate shape for `nrhs` right-hand sides in
+ * precision `prec` on this lattice (on library-owned scratch vectors, on `stream`), keeps the fastest
+ * for later stag_dslash / stag_cg_solve calls with the same key, and returns it in *best; if all is
+ * non-NULL, up to max_all timed candidates are written there and their count to *n_all.
+ * stag_set_dslash_shape pins a shape for the key (wg = 0 removes the entry).  The table is process-wide;
+ * stag_tune_cache_save / _load write and read it as JSON (path: a host C string). */
+stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, stag_shape* best, stag_shape* all,
+                             int32_t max_all, int32_t* n_all, void* stream);
+stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane);
+stag_status stag_tune_cache_save(const char* path);
+stag_status stag_tune_cache_load(const char* path);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* stag_last_error(void);

@@ -24,4 +24,4 @@ Staggered Fermions", Lattice 2010):
 
 Readings of the paper where it is silent are stated in each function.
 """
-from . import geometry, dslash, dense, free, cg, quant, cost, lowprec  # noqa: F401
+from . import geometry, dslash, dense, free, cg, fcg, quant, cost, lowprec, net  # noqa: F401

@@ -42,7 +42,8 @@ class StagParams(C.Structure):
         ("profile", C.c_int32),
         ("history_len", C.c_int32),
         ("history", C.POINTER(C.c_double)),
-        ("reserved", C.c_int32 * 8),
+        ("autotune", C.c_int32),
+        ("reserved", C.c_int32 * 7),
     ]
 
 
@@ -60,10 +61,16 @@ class StagInfo(C.Structure):
         ("dslash_calls", C.c_int32),
         ("dslash_prec", C.c_int32),
         ("dslash_sites", C.c_double),
+        ("dslash_wg", C.c_int32),
+        ("dslash_rhs", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class StagShape(C.Structure):
+    _fields_ = [("wg", C.c_int32), ("rhs_per_lane", C.c_int32), ("us", C.c_double)]
 
 
 class StagProblem(C.Structure):
@@ -90,6 +97,11 @@ SIGNATURES = {
                                 C.POINTER(StagParams), C.POINTER(StagInfo), C.c_void_p]),
     "stag_cg_solve_batch": (C.c_int, [C.c_int32, C.POINTER(StagProblem), C.POINTER(StagParams),
                                       C.POINTER(StagInfo), C.c_void_p]),
+    "stag_tune_dslash": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(StagShape), C.POINTER(StagShape),
+                                   C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
+    "stag_set_dslash_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "stag_tune_cache_save": (C.c_int, [C.c_char_p]),
+    "stag_tune_cache_load": (C.c_int, [C.c_char_p]),
 }
 
 _LIB = None

@@ -182,6 +182,11 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
   return STAG_OK;
 }
 
+std::string single_key(const BatchHost& bh, const stag_lattice_s* L, int prec) {
+  std::vector<const stag_lattice_s*> lats{L};
+  return tune_key(bh, lats, prec);
+}
+
 stag_status check_lattice(stag_lattice_t lat) {
   if (!lat) return arg_error("lattice is NULL");
   if (!lat->loaded) {
@@ -215,6 +220,7 @@ void stag_cg_params_default(stag_cg_params* prm) {
   prm->profile = 0;
   prm->history_len = 0;
   prm->history = nullptr;
+  prm->autotune = 0;
 }
 
 const char* stag_last_error(void) { return g_last_error.c_str(); }
@@ -323,7 +329,7 @@ stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, 
   RingEntry e;
   s = single_batch(lat, nrhs, nullptr, ov, st, bh, e);
   if (s != STAG_OK) return s;
-  const DslashShape sh = dslash_shape(lat, prec, nrhs, nrhs);
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec));
   STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
   if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, nsites, st));
   return ring_release(lat->ctl, e, st);
@@ -349,7 +355,7 @@ stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in,
   RingEntry e;
   s = single_batch(lat, nrhs, mass, ov, st, bh, e);
   if (s != STAG_OK) return s;
-  const DslashShape sh = dslash_shape(lat, P64, nrhs, nrhs);
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, P64));
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh.wg, sh.r, st));
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh.wg, sh.r, st));
   return ring_release(lat->ctl, e, st);
@@ -372,19 +378,83 @@ stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const 
   STAG_GUARD_END
 }
 
-}  // extern "C"
-
-namespace stag {
-
-DslashShape dslash_shape(const stag_lattice_s* lat, int prec, int nrhs, int total_rhs) {
-  (void)lat;
-  (void)prec;
-  (void)total_rhs;
-  DslashShape s;
-  s.wg = 256;
-  s.r = 1;
-  while (s.r < 8 && nrhs % (s.r * 2) == 0) s.r *= 2;
-  return s;
+stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, stag_shape* best, stag_shape* all,
+                             int32_t max_all, int32_t* n_all, void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (nrhs < 1) return arg_error("nrhs must be >= 1");
+  if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
+  if (!(lat->built & STAG_PREC_BIT(prec))) return arg_error("the requested precision was not packed by load_links");
+  if (all && max_all < 0) return arg_error("max_all must be >= 0");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  STAG_HIP_TRY(lat->vec[V_D].ensure(spinor_field_bytes(lat, prec, nrhs)));
+  STAG_HIP_TRY(lat->vec[V_T].ensure(spinor_field_bytes(lat, prec, nrhs)));
+  STAG_HIP_TRY(hipMemsetAsync(lat->vec[V_D].ptr, 0, spinor_field_bytes(lat, prec, nrhs), st));
+  void* ov[kNumVec] = {};
+  BatchHost bh;
+  RingEntry e;
+  s = single_batch(lat, nrhs, nullptr, ov, st, bh, e);
+  if (s != STAG_OK) return s;
+  DslashShape b{};
+  std::vector<std::pair<DslashShape, float>> timed;
+  STAG_HIP_TRY(tune_batch(bh, single_key(bh, lat, prec), prec, st, &b, &timed));
+  s = ring_release(lat->ctl, e, st);
+  if (s != STAG_OK) return s;
+  float best_us = 0.f;
+  for (const auto& t : timed)
+    if (t.first.wg == b.wg && t.first.r == b.r) best_us = t.second;
+  if (best) *best = stag_shape{b.wg, b.r, best_us};
+  if (all) {
+    int n = 0;
+    for (const auto& t : timed) {
+      if (n >= max_all) break;
+      all[n++] = stag_shape{t.first.wg, t.first.r, t.second};
+    }
+    if (n_all) *n_all = n;
+  }
+  return STAG_OK;
+  STAG_GUARD_END
 }
 
-}  // namespace stag
+stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane) {
+  STAG_GUARD_BEGIN
+  if (!lat) return arg_error("lattice is NULL");
+  if (nrhs < 1) return arg_error("nrhs must be >= 1");
+  if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
+  if (wg != 0 && wg != 64 && wg != 128 && wg != 256) return arg_error("wg must be 0, 64, 128 or 256");
+  if (wg != 0 && rhs_per_lane != 1 && rhs_per_lane != 2 && rhs_per_lane != 4 && rhs_per_lane != 8)
+    return arg_error("rhs_per_lane must be 1, 2, 4 or 8");
+  if (wg != 0 && nrhs % rhs_per_lane) return arg_error("rhs_per_lane must divide nrhs");
+  BatchHost bh;
+  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0});
+  pin_shape(single_key(bh, lat, prec), DslashShape{wg, rhs_per_lane});
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+stag_status stag_tune_cache_save(const char* path) {
+  STAG_GUARD_BEGIN
+  if (!path) return arg_error("path is NULL");
+  if (!save_table(path)) {
+    set_error(std::string("cannot write ") + path);
+    return STAG_ERR_ARG;
+  }
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+stag_status stag_tune_cache_load(const char* path) {
+  STAG_GUARD_BEGIN
+  if (!path) return arg_error("path is NULL");
+  int n = 0;
+  if (!load_table(path, &n)) {
+    set_error(std::string("cannot read a tuning table from ") + path);
+    return STAG_ERR_ARG;
+  }
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
+}  // extern "C"
+

@@ -76,8 +76,15 @@ namespace stag {
 // Fill the device-side description of a lattice (links of every built precision).
 ProbDev prob_dev(const stag_lattice_s* lat, int nrhs, int slot0);
 
-// Launch-shape choice for a Dslash; consults the autotuner cache.
-DslashShape dslash_shape(const stag_lattice_s* lat, int prec, int nrhs, int nprob_total_rhs);
+// Autotuner (autotune.cpp): launch shapes keyed by (precision, lattice shapes, right-hand sides).
+std::string tune_key(const BatchHost& bh, const std::vector<const stag_lattice_s*>& lats, int prec);
+DslashShape lookup_shape(const BatchHost& bh, const std::string& key);
+void pin_shape(const std::string& key, const DslashShape& s);
+bool has_shape(const std::string& key);
+hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hipStream_t st, DslashShape* best,
+                      std::vector<std::pair<DslashShape, float>>* all);
+bool save_table(const char* path);
+bool load_table(const char* path, int* n_loaded);
 
 // Solvers (solver.cpp).
 stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_params* prm, stag_cg_info* info,

@@ -25,7 +25,8 @@ struct Run {
   Ctl* ctl = nullptr;
   hipStream_t st = nullptr;
   int prec = P64;
-  DslashShape shape;
+  DslashShape shape;     // inner-iteration Dslash
+  DslashShape shape64;   // FP64 Dslash of the true residual
   int hist_len = 0;
   bool profile = false;
   std::vector<hipEvent_t>* events = nullptr;
@@ -79,7 +80,7 @@ hipError_t record(Run& R) {
 
 // V_R = b - M x (FP64), aux = ||V_R|| / ||b||, delta = |V_R|^2, for slots passing `gate`.
 hipError_t true_residual(Run& R, int gate) {
-  const DslashShape s64 = R.shape;
+  const DslashShape s64 = R.shape64;
   hipError_t e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_X, V_TMPO, 0, 0, gate, s64.wg, s64.r, R.st);
   if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_RESID, 0, V_TMPO, V_R, V_X, V_B, gate, s64.wg, s64.r, R.st);
   if (e == hipSuccess) e = launch_finalize(R.bh, FIN_TRUE, 1, gate, s64.wg, nullptr, 0, R.st);
@@ -148,7 +149,6 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
   R.bh.probs.clear();
   std::vector<ProbDev> table(nprob);
   int slot = 0;
-  int rdiv = 8;
   for (int p = 0; p < nprob; ++p) {
     stag_lattice_s* L = probs[p].lat;
     const int n = probs[p].nrhs;
@@ -171,7 +171,6 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     R.bh.probs.push_back(HostProb{L->g.half, n, slot});
     max_half = std::max(max_half, L->g.half);
     slot += n;
-    while (rdiv > 1 && n % rdiv) rdiv >>= 1;
   }
   R.bh.nslots = nslots;
   R.bh.max_half = max_half;
@@ -192,14 +191,17 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
   R.bh.d_partial = reinterpret_cast<double*>(ctl.partial.ptr);
   R.h_scal = reinterpret_cast<Scal*>(ctl.h_scal.ptr);
   R.events = &probs[0].lat->prof_events;
-  {
-    int total = 0;
-    for (int p = 0; p < nprob; ++p) total += probs[p].nrhs;
-    R.shape = dslash_shape(probs[0].lat, prm.prec, rdiv, total);
-    R.shape.r = std::min(R.shape.r, rdiv);
-  }
   std::memcpy(ctl.h_probs.ptr, table.data(), sizeof(ProbDev) * nprob);
   STAG_HIP_TRY(hipMemcpyAsync(ctl.probs.ptr, ctl.h_probs.ptr, sizeof(ProbDev) * nprob, hipMemcpyHostToDevice, st));
+  {
+    std::vector<const stag_lattice_s*> lats(R.lats.begin(), R.lats.end());
+    const std::string key = tune_key(R.bh, lats, prm.prec);
+    if (prm.autotune && !has_shape(key)) STAG_HIP_TRY(tune_batch(R.bh, key, prm.prec, st, nullptr, nullptr));
+    R.shape = lookup_shape(R.bh, key);
+    // the FP64 launches of the true residual use the FP64 key's shape
+    const std::string key64 = tune_key(R.bh, lats, P64);
+    R.shape64 = lookup_shape(R.bh, key64);
+  }
 
   // ---- scalars ----
   std::vector<int> passes(nslots, 0), iters(nslots, 0), n_rel(nslots, 0);
@@ -397,6 +399,8 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     o.dslash_calls = dcalls;
     o.dslash_prec = prm.prec;
     o.dslash_sites = sites;
+    o.dslash_wg = R.shape.wg;
+    o.dslash_rhs = R.shape.r;
     if (first_bad == STAG_OK && done_status[s] != STAG_OK) first_bad = (stag_status)done_status[s];
   }
   if (first_bad != STAG_OK)

@@ -12,9 +12,9 @@ from typing import Iterable, Sequence
 import torch
 
 from . import _lib
-from ._lib import PREC, StagError, StagInfo, StagParams, StagProblem, check, lib
+from ._lib import PREC, StagError, StagInfo, StagParams, StagProblem, StagShape, check, lib
 
-__all__ = ["Lattice", "cg_solve_batch", "StagError", "solve_params"]
+__all__ = ["Lattice", "cg_solve_batch", "StagError", "solve_params", "tune_cache_save", "tune_cache_load"]
 
 
 def _stream(stream=None) -> int:
@@ -38,7 +38,7 @@ def _dev_tensor(t: torch.Tensor, name: str, shape_tail=None) -> torch.Tensor:
 
 def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliable_delta=0.1, check_interval=16,
                  max_restarts=5, profile=False, history_len=0, history=None, stall_window=10,
-                 stall_ratio=0.9) -> StagParams:
+                 stall_ratio=0.9, autotune=False) -> StagParams:
     p = _lib.default_params()
     p.tol = tol
     p.prec = PREC[prec]
@@ -53,7 +53,16 @@ def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliab
         p.history = history.ctypes.data_as(C.POINTER(C.c_double))
     p.stall_window = stall_window
     p.stall_ratio = stall_ratio
+    p.autotune = 1 if autotune else 0
     return p
+
+
+def tune_cache_save(path: str):
+    check(lib().stag_tune_cache_save(path.encode()), "stag_tune_cache_save")
+
+
+def tune_cache_load(path: str):
+    check(lib().stag_tune_cache_load(path.encode()), "stag_tune_cache_load")
 
 
 class Lattice:
@@ -124,6 +133,20 @@ class Lattice:
         m = (C.c_double * nrhs)(*masses)
         check(lib().stag_apply_m(self._h, m, x.data_ptr(), out.data_ptr(), nrhs, _stream(stream)), "stag_apply_m")
         return out
+
+    def tune_dslash(self, prec: str = "f64", nrhs: int = 1, stream=None):
+        """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, us), ...])."""
+        best = StagShape()
+        all_ = (StagShape * 32)()
+        n = C.c_int32(0)
+        check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 32, C.byref(n),
+                                     _stream(stream)), "stag_tune_dslash")
+        return ((best.wg, best.rhs_per_lane, best.us),
+                [(all_[i].wg, all_[i].rhs_per_lane, all_[i].us) for i in range(n.value)])
+
+    def set_dslash_shape(self, prec: str, nrhs: int, wg: int, rhs_per_lane: int):
+        check(lib().stag_set_dslash_shape(self._h, PREC[prec], int(nrhs), int(wg), int(rhs_per_lane)),
+              "stag_set_dslash_shape")
 
     def cg_solve(self, b: torch.Tensor, mass, x0: torch.Tensor | None = None, raise_on_fail=True, stream=None,
                  **params):

@@ -235,3 +235,46 @@ def test_dslash_full_size_28cubed_96_sampled(gpu_lib):
         out = lat.dslash(torch.from_numpy(b).cuda(), par).cpu().numpy()
         ref = dslash_at_sites(fat, lng, b, dims, par, sample)
         assert rel(out[sample], ref) <= 1e-12
+
+
+def test_dslash_identical_for_every_launch_shape(gpu_lib):
+    """Workgroup size and right-hand sides per lane change the schedule, not the arithmetic: bitwise equal."""
+    dims = (6, 4, 6, 8)
+    print("dslash launch shapes", flush=True)
+    lat, fat, lng = make(dims, seed=91, precs=("f64", "f16"))
+    b = torch.from_numpy(gaussian_source(dims, 92, 8)).cuda()
+    for prec in ("f64", "f16"):
+        ref = None
+        for wg in (64, 128, 256):
+            for r in (1, 2, 4, 8):
+                lat.set_dslash_shape(prec, 8, wg, r)
+                out = lat.dslash(b, 1, prec=prec)
+                if ref is None:
+                    ref = out.clone()
+                assert torch.equal(out, ref), (prec, wg, r)
+        lat.set_dslash_shape(prec, 8, 0, 1)
+    assert rel(ref.cpu().numpy()[3], dslash_eo(fat, lng, b.cpu().numpy()[3], dims, 1)) > 0  # f16 result exists
+    best, timed = lat.tune_dslash("f16", 8)
+    assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and len(timed) == 12
+    assert all(t[2] > 0 for t in timed)
+
+
+def test_batched_solve_with_autotune(gpu_lib):
+    from paper_1010_4782_amd.stagcg import cg_solve_batch
+
+    print("batched solve autotune", flush=True)
+    probs, refs = [], []
+    for i, (dims, nrhs) in enumerate([((4, 4, 4, 8), 4), ((6, 6, 4, 4), 8)]):
+        lat, fat, lng = make(dims, seed=95 + i, precs=("f64", "f16"))
+        b = gaussian_source(dims, 97 + i, nrhs)
+        probs.append((lat, torch.from_numpy(b).cuda(), [0.05] * nrhs, None))
+        refs.append((fat, lng, dims, b))
+    xs, infos = cg_solve_batch(probs, tol=1e-10, prec="f16", autotune=True)
+    assert infos[0]["dslash_rhs"] in (1, 2, 4)
+    k = 0
+    for (fat, lng, dims, b), x in zip(refs, xs):
+        x = x.cpu().numpy()
+        for r in range(len(b)):
+            assert infos[k]["converged"] == 1
+            assert true_residual(lambda v: apply_m(fat, lng, v, dims, 0.05), b[r], x[r]) <= 1.05e-10
+            k += 1
