@@ -74,8 +74,9 @@ typedef struct {
                                 at the previous update (default 0.1; <= 0 disables this trigger) */
   int32_t check_interval;    /* iterations between host convergence polls (default 16) */
   int32_t max_restarts;      /* true-residual restarts after the iterated residual converged (default 5) */
-  int32_t precond;           /* stag_precond */
-  stag_net_t net;            /* network for STAG_PRECOND_NET */
+  int32_t precond;           /* stag_precond; STAG_PRECOND_NET runs flexible CG (single problem only) with the
+                                network as preconditioner, then plain CG if it stalls or breaks down */
+  stag_net_t net;            /* network for STAG_PRECOND_NET (built on the solve's lattice) */
   int32_t stall_window;      /* FCG: fall back to plain CG if ||r_k|| > stall_ratio ||r_{k-w}|| (default 10) */
   double stall_ratio;        /* default 0.9 */
   int32_t profile;           /* 1: time every Dslash launch with HIP events (stag_cg_info.dslash_ms) */
@@ -183,6 +184,52 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
 stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane);
 stag_status stag_tune_cache_save(const char* path);
 stag_status stag_tune_cache_load(const char* path);
+
+/* Learned preconditioner (the project's third change to the method; the paper has none): a
+ * gauge-covariant linear network.  Layer l maps ch[l] to ch[l+1] colour-vector channels on the full
+ * lattice, y_c(n) = sum_c' [W_0 psi_c'(n) + sum_{d=1..8} W_d (T_d psi_c')(n)] with T_{+mu}, T_{-mu} the
+ * parallel transports along the one-hop links (phases and boundary signs folded in, as in Eq. (5)).
+ * Channels run 1 -> channels -> ... -> channels -> 1; the input is an even-site vector embedded on the
+ * full lattice, the output its restriction to even sites.  Activations are complex64.
+ * Weights (host) are complex128, concatenated per layer as [9][ch[l+1]][ch[l]] with direction order
+ * d = 0 (site), 1..4 (+x,+y,+z,+t), 5..8 (-x,-y,-z,-t).
+ * The network needs the lattice's FP32 links (stag_load_links with STAG_PREC_BIT(STAG_F32)); it keeps
+ * pointers into them, so reload links only with the same lattice and destroy nets before the lattice.
+ * channels: 1, 2, 4 or 8; layers in [1, 16]; seed: initial weights. */
+stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint64_t seed, stag_net_t* out);
+stag_status stag_net_destroy(stag_net_t net);
+stag_status stag_net_num_weights(stag_net_t net, int64_t* n_complex);
+stag_status stag_net_set_weights(stag_net_t net, const double* w, int64_t n_complex);   /* host complex128 */
+stag_status stag_net_get_weights(stag_net_t net, double* w, int64_t n_complex);
+/* out = N(in) for nrhs even-site vectors: device complex128 [nrhs][V/2][3]; in and out must not overlap. */
+stag_status stag_net_apply(stag_net_t net, const void* in, void* out, int32_t nrhs, void* stream);
+/* Loss L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2 over npairs pairs (device complex128 [npairs][V/2][3] each)
+ * and, if grad is not NULL, dL/dconj(W) in the weight layout (host complex128).  Synchronises. */
+stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, double* loss,
+                               double* grad, void* stream);
+
+typedef struct {
+  int32_t epochs;            /* passes over the training pairs (default 10) */
+  int32_t batch;             /* pairs per optimiser step (default 8) */
+  double lr;                 /* Adam step size (default 1e-3) */
+  double beta1, beta2, eps;  /* Adam moments (0.9, 0.999, 1e-8) */
+  uint64_t seed;             /* shuffling of the pairs (default 1) */
+  int32_t reserved[8];
+} stag_train_params;
+
+typedef struct {
+  double loss_first;         /* mean loss over the pairs in the first epoch */
+  double loss_last;          /* ... in the last epoch */
+  int32_t epochs;
+  int32_t steps;             /* optimiser steps taken */
+  double ms;                 /* wall time */
+} stag_train_info;
+
+void stag_train_params_default(stag_train_params* prm);
+/* Train the weights with Adam on (b_i, x_i = M^{-1} b_i) pairs (device complex128 [npairs][V/2][3]),
+ * minimising the loss of stag_net_loss_grad.  Synchronises. */
+stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t npairs,
+                           const stag_train_params* prm, stag_train_info* info, void* stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* stag_last_error(void);

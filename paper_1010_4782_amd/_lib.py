@@ -83,6 +83,29 @@ class StagProblem(C.Structure):
     ]
 
 
+class StagTrainParams(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int32),
+        ("batch", C.c_int32),
+        ("lr", C.c_double),
+        ("beta1", C.c_double),
+        ("beta2", C.c_double),
+        ("eps", C.c_double),
+        ("seed", C.c_uint64),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+
+class StagTrainInfo(C.Structure):
+    _fields_ = [
+        ("loss_first", C.c_double),
+        ("loss_last", C.c_double),
+        ("epochs", C.c_int32),
+        ("steps", C.c_int32),
+        ("ms", C.c_double),
+    ]
+
+
 # name -> (restype, argtypes); every function of include/stagcg.h
 SIGNATURES = {
     "stag_cg_params_default": (None, [C.POINTER(StagParams)]),
@@ -102,6 +125,17 @@ SIGNATURES = {
     "stag_set_dslash_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "stag_tune_cache_save": (C.c_int, [C.c_char_p]),
     "stag_tune_cache_load": (C.c_int, [C.c_char_p]),
+    "stag_net_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "stag_net_destroy": (C.c_int, [C.c_void_p]),
+    "stag_net_num_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "stag_net_set_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
+    "stag_net_get_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
+    "stag_net_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "stag_net_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_void_p]),
+    "stag_train_params_default": (None, [C.POINTER(StagTrainParams)]),
+    "stag_net_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(StagTrainParams),
+                                 C.POINTER(StagTrainInfo), C.c_void_p]),
 }
 
 _LIB = None

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstagcg.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["pack.hip", "dslash.hip", "blas.hip", "solver.cpp", "autotune.cpp", "capi.cpp"]
+SOURCES = ["pack.hip", "dslash.hip", "blas.hip", "net.hip", "solver.cpp", "autotune.cpp", "net.cpp", "capi.cpp"]
 
 # Packed FP32 instructions are disabled for all device code: they are not needed
 # for this bandwidth-bound path, and the build must not emit them.
@@ -36,7 +36,7 @@ def hipcc() -> str:
 
 
 def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
     path = os.path.join(CSRC, src)
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
     cmd = [hipcc()] + lang + HIP_FLAGS + ["-c", path, "-o", obj]

@@ -205,6 +205,92 @@ __global__ __launch_bounds__(kMaxWG) void k_d_fix(Batch B, int gate) {
   store_spinor<P>(dp, m.cb, d);
 }
 
+// ---- flexible CG (FP64 vectors) ----------------------------------------------------
+// d = z + beta d (complex beta from FIN_FCG_BETA; 0 on the first iteration); partial kinds 1, 2 = Re, Im <d, r>.
+__global__ __launch_bounds__(kMaxWG) void k_fcg_dir(Batch B, int gate) {
+  __shared__ double lds[8];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate)) return;
+  const double br = B.scal[m.slot].br, bi = B.scal[m.slot].bi;
+  double s[2] = {0.0, 0.0};
+  if (m.live) {
+    Cx<double> z[3], d[3], r[3];
+    char* dp = vec_ptr<P64>(m, V_D);
+    load_spinor<P64>(vec_ptr<P64>(m, V_Z), m.cb, z);
+    load_spinor<P64>(dp, m.cb, d);
+    load_spinor<P64>(vec_ptr<P64>(m, V_R), m.cb, r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const Cx<double> nd{z[c].re + br * d[c].re - bi * d[c].im, z[c].im + br * d[c].im + bi * d[c].re};
+      d[c] = nd;
+      s[0] += nd.re * r[c].re + nd.im * r[c].im;
+      s[1] += nd.re * r[c].im - nd.im * r[c].re;
+    }
+    store_spinor<P64>(dp, m.cb, d);
+  }
+  block_sum<2>(s, lds);
+  if (threadIdx.x == 0) {
+    B.partial[((long)m.slot * kPartialSlots + 1) * B.pstride + m.tile] = s[0];
+    B.partial[((long)m.slot * kPartialSlots + 2) * B.pstride + m.tile] = s[1];
+  }
+}
+
+// x += alpha d ; r -= alpha Ad (complex alpha) ; partial kind 1 = |r|^2
+__global__ __launch_bounds__(kMaxWG) void k_fcg_update(Batch B) {
+  __shared__ double lds[4];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, 1)) return;
+  const double ar = B.scal[m.slot].ar, ai = B.scal[m.slot].ai;
+  double s[1] = {0.0};
+  if (m.live) {
+    Cx<double> x[3], d[3], r[3], a[3];
+    char* xp = vec_ptr<P64>(m, V_X);
+    char* rp = vec_ptr<P64>(m, V_R);
+    load_spinor<P64>(xp, m.cb, x);
+    load_spinor<P64>(vec_ptr<P64>(m, V_D), m.cb, d);
+    load_spinor<P64>(rp, m.cb, r);
+    load_spinor<P64>(vec_ptr<P64>(m, V_AD), m.cb, a);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c].re += ar * d[c].re - ai * d[c].im;
+      x[c].im += ar * d[c].im + ai * d[c].re;
+      r[c].re -= ar * a[c].re - ai * a[c].im;
+      r[c].im -= ar * a[c].im + ai * a[c].re;
+      s[0] += r[c].re * r[c].re + r[c].im * r[c].im;
+    }
+    store_spinor<P64>(xp, m.cb, x);
+    store_spinor<P64>(rp, m.cb, r);
+  }
+  block_sum<1>(s, lds);
+  write_partial(B, m, 1, s[0]);
+}
+
+// partial kinds 1, 2 = Re, Im <Ad, z>
+__global__ __launch_bounds__(kMaxWG) void k_fcg_beta_dot(Batch B, int gate) {
+  __shared__ double lds[8];
+  VecMap m;
+  map_vec_block(B, m);
+  if (!slot_on(B.scal, m.slot, gate)) return;
+  double s[2] = {0.0, 0.0};
+  if (m.live) {
+    Cx<double> a[3], z[3];
+    load_spinor<P64>(vec_ptr<P64>(m, V_AD), m.cb, a);
+    load_spinor<P64>(vec_ptr<P64>(m, V_Z), m.cb, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s[0] += a[c].re * z[c].re + a[c].im * z[c].im;
+      s[1] += a[c].re * z[c].im - a[c].im * z[c].re;
+    }
+  }
+  block_sum<2>(s, lds);
+  if (threadIdx.x == 0) {
+    B.partial[((long)m.slot * kPartialSlots + 1) * B.pstride + m.tile] = s[0];
+    B.partial[((long)m.slot * kPartialSlots + 2) * B.pstride + m.tile] = s[1];
+  }
+}
+
 // One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.
 __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
                                                   double* hist, int hist_stride) {
@@ -214,7 +300,7 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
   while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
   if (!slot_on(B.scal, slot, gate)) return;
   const int ntiles = ceil_div(B.probs[p].g.half, producer_wg);
-  const int nk = what == FIN_ORTHO ? 3 : 1;
+  const int nk = (what == FIN_ORTHO || what == FIN_FCG_ALPHA) ? 3 : (what == FIN_FCG_BETA ? 2 : 1);
   double s[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < nk; ++k) {
     const double* src = B.partial + ((long)slot * kPartialSlots + kind + k) * B.pstride;
@@ -283,6 +369,39 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
       break;
     case FIN_RELIABLE:
       sc.delta = sum;
+      break;
+    case FIN_FCG_ALPHA:
+      if (sc.state != 0) break;
+      sc.dAd = sum;
+      if (!(sum > 0.0) || !isfinite(sum) || !isfinite(s[1]) || !isfinite(s[2])) {
+        sc.flags |= kFlagBreakdown;
+        sc.state = 2;
+        break;
+      }
+      sc.ar = s[1] / sum;
+      sc.ai = s[2] / sum;
+      if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2] = sc.ar;
+      break;
+    case FIN_FCG_RES:
+      if (sc.state != 0) break;
+      if (!isfinite(sum)) {
+        sc.flags |= kFlagBreakdown;
+        sc.state = 2;
+        break;
+      }
+      sc.delta_old = sc.delta;
+      sc.delta = sum;
+      sc.iter += 1;
+      if (sum <= sc.thr) sc.state = 1;
+      if (sc.iter >= sc.max_iter) {
+        sc.state = 1;
+        sc.flags |= kFlagMaxIter;
+      }
+      break;
+    case FIN_FCG_BETA:
+      if (sc.state != 0) break;
+      sc.br = -sum / sc.dAd;
+      sc.bi = -s[1] / sc.dAd;
       break;
     case FIN_ORTHO: {
       const double n2 = s[2];
@@ -369,6 +488,30 @@ hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStre
   const int nb = nblocks(B);
   if (nb == 0) return hipSuccess;
   STAG_PREC_SWITCH(prec, k_d_fix, B, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  k_fcg_dir<<<nb, wg, 0, st>>>(B, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_update(const BatchHost& bh, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  k_fcg_update<<<nb, wg, 0, st>>>(B);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_beta_dot(const BatchHost& bh, int gate, int wg, hipStream_t st) {
+  const Batch B = make_batch(bh, wg, 1);
+  const int nb = nblocks(B);
+  if (nb == 0) return hipSuccess;
+  k_fcg_beta_dot<<<nb, wg, 0, st>>>(B, gate);
   return hipGetLastError();
 }
 

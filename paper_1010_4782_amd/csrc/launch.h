@@ -56,8 +56,15 @@ enum Fin : int {
   FIN_BETA = 3,      // delta_old = delta ; delta = sum ; beta ; iter++ ; stop test
   FIN_TRUE = 4,      // aux = sqrt(sum / b2) (true residual)
   FIN_RELIABLE = 5,  // delta = sum (after the FP64 residual recomputation)
-  FIN_ORTHO = 6      // kinds 0,1,2 = Re<r,d>, Im<r,d>, |r|^2: c = 1 - <r,d>/|r|^2 ; delta = |r|^2
+  FIN_ORTHO = 6,     // kinds 0,1,2 = Re<r,d>, Im<r,d>, |r|^2: c = 1 - <r,d>/|r|^2 ; delta = |r|^2
+  FIN_FCG_ALPHA = 7, // kinds 0,1,2 = <d,Ad>, Re<d,r>, Im<d,r>: alpha = <d,r>/<d,Ad> (breakdown -> flag, state 2)
+  FIN_FCG_RES = 8,   // kind 1 = |r|^2: delta, iter++, stop test
+  FIN_FCG_BETA = 9   // kinds 1,2 = Re<Ad,z>, Im<Ad,z>: beta = -<Ad,z>/<d,Ad>
 };
+// Flexible CG vector stages (FP64; z, d, r, Ad, x are the V_Z, V_D, V_R, V_AD, V_X roles).
+hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st);     // d = z + beta d ; <d,r>
+hipError_t launch_fcg_update(const BatchHost& bh, int wg, hipStream_t st);            // x += a d ; r -= a Ad ; |r|^2
+hipError_t launch_fcg_beta_dot(const BatchHost& bh, int gate, int wg, hipStream_t st); // <Ad, z>
 // Mixed precision, after a reliable update: restore <d, r> = |r|^2 for the new residual r.
 hipError_t launch_rd_dot(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);
 hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);

@@ -1,0 +1,294 @@
+// Kernels of the gauge-covariant linear network used as the flexible-CG preconditioner.
+//
+// A layer maps C_in colour-vector channels to C_out on the full lattice:
+//   y_c(n) = sum_c' [ W_0[c][c'] psi_c'(n) + sum_{d=1..8} W_d[c][c'] (T_d psi_c')(n) ]
+// with T_{+mu} psi(n) = F~_mu(n) psi(n+mu) and T_{-mu} psi(n) = F~_mu(n-mu)^dag psi(n-mu)
+// (d = 1..4: +x,+y,+z,+t; d = 5..8: -x,-y,-z,-t).  The transports reuse the packed FP32
+// one-hop matrices of the Dslash: for output parity p, k = 4 mu is F~_mu(n) and
+// k = 4 mu + 1 is -F~_mu(n-mu)^dag, so T_{-mu} = -L_{4mu+1}.
+//
+// Activations are complex64 and stored per parity: [parity][channel][V/2] x 3 colours.
+// A null input pointer stands for a field that is zero on that parity.
+#include "device.h"
+#include "net.h"
+#include "launch.h"
+
+namespace stag {
+
+__device__ __forceinline__ void cmac_f(Cx<float>& acc, const float2 w, const Cx<float>& v) {
+  acc.re = fmaf(w.x, v.re, acc.re);
+  acc.re = fmaf(-w.y, v.im, acc.re);
+  acc.im = fmaf(w.x, v.im, acc.im);
+  acc.im = fmaf(w.y, v.re, acc.im);
+}
+
+// Transported colour vectors of all input channels along direction d (1..8) for the site s.
+template <int CIN>
+__device__ __forceinline__ void transported(const NetLayerArgs& a, const Site& s, long blk, int lane, int d,
+                                            Cx<float> t[CIN][3]) {
+  const int mu = (d - 1) & 3;
+  const bool fwd = d <= 4;
+  const int nb = neighbour(s, a.g, mu, a.g.h1[mu], fwd);
+  Cx<float> u[9];
+  load_link<P32>(a.links, blk, 4 * mu + (fwd ? 0 : 1), lane, 1.f, u);
+  if (!fwd)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = Cx<float>{-u[e].re, -u[e].im};
+#pragma unroll
+  for (int c = 0; c < CIN; ++c) {
+    Cx<float> v[3];
+    load_spinor<P32>(a.in_other + (long)c * a.g.half * 3, nb, v);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[c][i] = Cx<float>{0.f, 0.f};
+    matvec_acc(u, v, t[c]);
+  }
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_net_layer(NetLayerArgs a) {
+  const int cb_raw = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cb_raw >= a.g.half) return;
+  const int cb = cb_raw;
+  const Site s = site_of(cb, a.out_par, a.g);
+  const long blk = cb >> 6;
+  const int lane = cb & 63;
+  Cx<float> acc[COUT][3];
+#pragma unroll
+  for (int c = 0; c < COUT; ++c)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[c][i] = Cx<float>{0.f, 0.f};
+  if (a.in_same) {
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+      Cx<float> v[3];
+      load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, v);
+#pragma unroll
+      for (int c = 0; c < COUT; ++c) {
+        const float2 w = a.w[c * CIN + ci];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) cmac_f(acc[c][i], w, v[i]);
+      }
+    }
+  }
+  if (a.in_other) {
+#pragma unroll 1
+    for (int d = 1; d <= 8; ++d) {
+      Cx<float> t[CIN][3];
+      transported<CIN>(a, s, blk, lane, d, t);
+      const float2* wd = a.w + d * COUT * CIN;
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+        for (int c = 0; c < COUT; ++c) {
+          const float2 w = wd[c * CIN + ci];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) cmac_f(acc[c][i], w, t[ci][i]);
+        }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < COUT; ++c) store_spinor<P32>(a.out + (long)c * a.g.half * 3, cb, acc[c]);
+}
+
+// Weight gradient, one direction d (blockIdx.y) and a group of G output channels (blockIdx.z):
+//   partial[p][d][c][c'] = sum_n sum_a G_c(n)_a conj((T_d psi_c')(n)_a)
+// over the output sites of parity a.out_par; each block walks sites with a grid stride and
+// writes one partial (complex, FP64) per (d, c, c') for a fixed-order second stage.
+template <int CIN, int COUT, int G>
+__global__ __launch_bounds__(256) void k_net_wgrad(NetLayerArgs a, const float2* gy, double* partial) {
+  const int d = blockIdx.y;
+  const int cg = blockIdx.z;
+  Cx<float> acc[G][CIN];
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) acc[c][ci] = Cx<float>{0.f, 0.f};
+  const bool have = d == 0 ? a.in_same != nullptr : a.in_other != nullptr;
+  if (have && gy) {
+    for (int cb = blockIdx.x * blockDim.x + threadIdx.x; cb < a.g.half; cb += gridDim.x * blockDim.x) {
+      const Site s = site_of(cb, a.out_par, a.g);
+      Cx<float> t[CIN][3];
+      if (d == 0) {
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+      } else {
+        transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
+      }
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        Cx<float> gv[3];
+        load_spinor<P32>(gy + (long)(cg * G + c) * a.g.half * 3, cb, gv);
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            // g * conj(t)
+            acc[c][ci].re = fmaf(gv[i].re, t[ci][i].re, acc[c][ci].re);
+            acc[c][ci].re = fmaf(gv[i].im, t[ci][i].im, acc[c][ci].re);
+            acc[c][ci].im = fmaf(gv[i].im, t[ci][i].re, acc[c][ci].im);
+            acc[c][ci].im = fmaf(-gv[i].re, t[ci][i].im, acc[c][ci].im);
+          }
+      }
+    }
+  }
+  // block reduction, one (c, c') pair at a time, in FP64
+  __shared__ double lds[2 * 4];
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+      double v[2] = {(double)acc[c][ci].re, (double)acc[c][ci].im};
+      block_sum<2>(v, lds);
+      if (threadIdx.x == 0) {
+        const int co = cg * G + c;
+        const long idx = ((((long)a.out_par * 9 + d) * COUT + co) * CIN + ci) * gridDim.x + blockIdx.x;
+        partial[2 * idx] = v[0];
+        partial[2 * idx + 1] = v[1];
+      }
+      __syncthreads();
+    }
+}
+
+// out[d][c][c'] = sum over parities and blocks of the partials, in a fixed order.
+__global__ __launch_bounds__(64) void k_net_wgrad_reduce(const double* partial, int cin, int cout, int nblk,
+                                                         int npar, double* out) {  // out += sum
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;  // (d, c, c') flat
+  const int n = 9 * cout * cin;
+  if (j >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < npar; ++p)
+    for (int b = 0; b < nblk; ++b) {
+      const long idx = ((long)p * n + j) * nblk + b;
+      re += partial[2 * idx];
+      im += partial[2 * idx + 1];
+    }
+  out[2 * j] += re;
+  out[2 * j + 1] += im;
+}
+
+// even-site complex128 vector -> channel 0 of a complex64 activation (parity 0)
+__global__ __launch_bounds__(256) void k_net_embed(const double2* in, float2* out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = in[i];
+  out[i] = make_float2((float)v.x, (float)v.y);
+}
+
+// channel 0 of a complex64 activation (parity 0) -> even-site complex128 vector
+__global__ __launch_bounds__(256) void k_net_extract(const float2* in, double2* out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 v = in[i];
+  out[i] = make_double2((double)v.x, (double)v.y);
+}
+
+// Loss gradient at the output: g = scale (N(b) - x) on even sites; partial |N(b) - x|^2 per block.
+__global__ __launch_bounds__(256) void k_net_loss(const float2* out, const double2* x, double scale, float2* g,
+                                                  double* partial, long n) {
+  __shared__ double lds[4];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s[1] = {0.0};
+  if (i < n) {
+    const float2 o = out[i];
+    const double2 xv = x[i];
+    const double dr = (double)o.x - xv.x, di = (double)o.y - xv.y;
+    s[0] = dr * dr + di * di;
+    g[i] = make_float2((float)(scale * dr), (float)(scale * di));
+  }
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double lds[4];
+  double s[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s[0] += partial[i];
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+// ---- launchers ---------------------------------------------------------------------
+hipError_t launch_net_layer(const NetLayerArgs& a, int cin, int cout, hipStream_t st) {
+  const int nb = ceil_div(a.g.half, 256);
+#define STAG_NET_LAYER(I, O) \
+  if (cin == I && cout == O) { k_net_layer<I, O><<<nb, 256, 0, st>>>(a); return hipGetLastError(); }
+  STAG_NET_LAYER(1, 1) STAG_NET_LAYER(1, 2) STAG_NET_LAYER(2, 1) STAG_NET_LAYER(2, 2)
+  STAG_NET_LAYER(1, 4) STAG_NET_LAYER(4, 1) STAG_NET_LAYER(4, 4)
+  STAG_NET_LAYER(1, 8) STAG_NET_LAYER(8, 1) STAG_NET_LAYER(8, 8)
+#undef STAG_NET_LAYER
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_net_wgrad(const NetLayerArgs& a, const float2* gy, double* partial, int cin, int cout, int nblk,
+                            hipStream_t st) {
+#define STAG_NET_WG(I, O, G)                                                  \
+  if (cin == I && cout == O) {                                                \
+    k_net_wgrad<I, O, G><<<dim3(nblk, 9, O / G), 256, 0, st>>>(a, gy, partial); \
+    return hipGetLastError();                                                 \
+  }
+  STAG_NET_WG(1, 1, 1) STAG_NET_WG(1, 2, 2) STAG_NET_WG(2, 1, 1) STAG_NET_WG(2, 2, 2)
+  STAG_NET_WG(1, 4, 4) STAG_NET_WG(4, 1, 1) STAG_NET_WG(4, 4, 4)
+  STAG_NET_WG(1, 8, 8) STAG_NET_WG(8, 1, 1) STAG_NET_WG(8, 8, 4)
+#undef STAG_NET_WG
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_net_wgrad_reduce(const double* partial, int cin, int cout, int nblk, int npar, double* out,
+                                   hipStream_t st) {
+  const int n = 9 * cout * cin;
+  k_net_wgrad_reduce<<<ceil_div(n, 64), 64, 0, st>>>(partial, cin, cout, nblk, npar, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_embed(const void* in, float2* out, long nsites, hipStream_t st) {
+  const long n = nsites * 3;
+  if (n == 0) return hipSuccess;
+  k_net_embed<<<(n + 255) / 256, 256, 0, st>>>(reinterpret_cast<const double2*>(in), out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_extract(const float2* in, void* out, long nsites, hipStream_t st) {
+  const long n = nsites * 3;
+  if (n == 0) return hipSuccess;
+  k_net_extract<<<(n + 255) / 256, 256, 0, st>>>(in, reinterpret_cast<double2*>(out), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_loss(const float2* out, const void* x, double scale, float2* g, double* partial, double* sum,
+                           long nsites, hipStream_t st) {
+  const long n = nsites * 3;
+  const int nb = (int)((n + 255) / 256);
+  k_net_loss<<<nb, 256, 0, st>>>(out, reinterpret_cast<const double2*>(x), scale, g, partial, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum_partials<<<1, 256, 0, st>>>(partial, nb, sum);
+  return hipGetLastError();
+}
+
+}  // namespace stag
+
+namespace stag {
+
+__global__ __launch_bounds__(256) void k_norm2_c128(const double2* x, double* partial, long n) {
+  __shared__ double lds[4];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s[1] = {0.0};
+  if (i < n) {
+    const double2 v = x[i];
+    s[0] = v.x * v.x + v.y * v.y;
+  }
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+hipError_t launch_norm2_c128(const void* x, double* partial, double* sum, long nsites, hipStream_t st) {
+  const long n = nsites * 3;
+  const int nb = (int)((n + 255) / 256);
+  k_norm2_c128<<<nb, 256, 0, st>>>(reinterpret_cast<const double2*>(x), partial, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum_partials<<<1, 256, 0, st>>>(partial, nb, sum);
+  return hipGetLastError();
+}
+
+}  // namespace stag

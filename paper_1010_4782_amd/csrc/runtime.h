@@ -86,6 +86,10 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
 bool save_table(const char* path);
 bool load_table(const char* path, int* n_loaded);
 
+// Network (net.cpp).
+stag_lattice_s* net_lattice(stag_net_s* n);
+hipError_t net_forward(stag_net_s* n, const void* in, void* out, hipStream_t st);
+
 // Solvers (solver.cpp).
 stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_params* prm, stag_cg_info* info,
                         hipStream_t st);

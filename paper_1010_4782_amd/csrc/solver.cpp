@@ -102,6 +102,110 @@ hipError_t iteration(Run& R, int x_prec, int x_id, double* d_hist) {
   return e;
 }
 
+// Flexible CG with the network preconditioner (FP64 vectors and operator):
+//   z = N(r); beta = -<A d_prev, z> / <d_prev, A d_prev>; d = z + beta d;
+//   alpha = <d, r> / <d, A d>; x += alpha d; r -= alpha A d.
+// Every stall_window iterations the host compares ||r|| with its value one window earlier; a slot
+// that did not drop below stall_ratio times that value (or broke down) leaves the phase and the
+// plain-CG passes that follow finish it from its current x.
+stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb, double* d_hist, std::vector<int>& iters,
+                      std::vector<int>& fell_back) {
+  const int nslots = R.bh.nslots;
+  const int half = R.bh.probs[0].half;
+  const size_t vb = (size_t)half * 48;
+  stag_lattice_s* L = pb.lat;
+  char* rbase = reinterpret_cast<char*>(L->vec[V_R].ptr);
+  char* zbase = reinterpret_cast<char*>(L->vec[V_Z].ptr);
+  const int window = prm.stall_window > 0 ? prm.stall_window : 10;
+  const double ratio2 = prm.stall_ratio * prm.stall_ratio;
+  STAG_HIP_TRY(pull_scal(R, "fcg-start"));
+  std::vector<double> prev(nslots, 0.0);
+  std::vector<char> part(nslots, 0);
+  std::vector<int> saved(nslots);
+  bool any = false;
+  for (int s = 0; s < nslots; ++s) {
+    Scal& sc = R.h_scal[s];
+    saved[s] = sc.state;
+    if (sc.state == 3 || sc.aux <= prm.tol) {  // zero source or already converged: not in the phase
+      sc.state = 3;
+      continue;
+    }
+    sc.state = 0;
+    sc.iter = 0;
+    sc.flags = 0;
+    sc.br = sc.bi = 0.0;
+    prev[s] = sc.delta;
+    part[s] = 1;
+    any = true;
+  }
+  if (!any) {
+    for (int s = 0; s < nslots; ++s) R.h_scal[s].state = saved[s];
+    STAG_HIP_TRY(push_scal(R));
+    return STAG_OK;
+  }
+  STAG_HIP_TRY(push_scal(R));
+  auto apply_net = [&]() -> hipError_t {
+    for (int r = 0; r < nslots; ++r) {
+      hipError_t e = net_forward(prm.net, rbase + r * vb, zbase + r * vb, R.st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  STAG_HIP_TRY(apply_net());
+  STAG_HIP_TRY(launch_zero_vec(R.bh, P64, V_D, 1, kVecWG, R.st));
+  STAG_HIP_TRY(launch_fcg_dir(R.bh, 1, kVecWG, R.st));  // d = z, <d, r>
+  for (;;) {
+    for (int i = 0; i < window; ++i) {
+      hipError_t e = record(R);
+      if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape64.wg, R.shape64.r, R.st);
+      if (e == hipSuccess) e = record(R);
+      if (e == hipSuccess)
+        e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64.wg, R.shape64.r, R.st);
+      if (e == hipSuccess) e = record(R);
+      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, R.shape64.wg, d_hist, R.hist_len, R.st);
+      if (e == hipSuccess) e = launch_fcg_update(R.bh, kVecWG, R.st);
+      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_RES, 1, 1, kVecWG, nullptr, 0, R.st);
+      if (e == hipSuccess) e = apply_net();
+      if (e == hipSuccess) e = launch_fcg_beta_dot(R.bh, 1, kVecWG, R.st);
+      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_BETA, 1, 1, kVecWG, nullptr, 0, R.st);
+      if (e == hipSuccess) e = launch_fcg_dir(R.bh, 1, kVecWG, R.st);
+      STAG_HIP_TRY(e);
+    }
+    STAG_HIP_TRY(pull_scal(R, "poll-fcg"));
+    bool running = false;
+    for (int s = 0; s < nslots; ++s) {
+      Scal& sc = R.h_scal[s];
+      if (sc.state != 0) {
+        if (sc.state == 2 && (sc.flags & kFlagBreakdown)) fell_back[s] = 1;
+        continue;
+      }
+      if (sc.delta > ratio2 * prev[s]) {
+        fell_back[s] = 1;
+        sc.state = 2;
+      } else {
+        prev[s] = sc.delta;
+        running = true;
+      }
+    }
+    STAG_HIP_TRY(push_scal(R));
+    if (!running) break;
+  }
+  // hand the participants back to the outer loop (state 2: classify) and restore the others
+  for (int s = 0; s < nslots; ++s) {
+    Scal& sc = R.h_scal[s];
+    if (!part[s]) {
+      sc.state = saved[s];
+      continue;
+    }
+    iters[s] += sc.iter;
+    sc.iter = 0;
+    sc.flags &= ~(kFlagBreakdown | kFlagMaxIter);
+    sc.state = 2;
+  }
+  STAG_HIP_TRY(push_scal(R));
+  return STAG_OK;
+}
+
 }  // namespace
 
 stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_params* prm_in, stag_cg_info* info,
@@ -113,7 +217,14 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
   if (!probs || !info) return fail_arg("probs and info must not be NULL");
   if (!(prm.tol > 0.0) || !std::isfinite(prm.tol)) return fail_arg("tol must be a positive finite number");
   if (prm.prec < STAG_F64 || prm.prec > STAG_F16) return fail_arg("prec must be STAG_F64, STAG_F32 or STAG_F16");
-  if (prm.precond != STAG_PRECOND_NONE) return fail_arg("this entry point solves without a preconditioner; use the FCG driver");
+  if (prm.precond != STAG_PRECOND_NONE && prm.precond != STAG_PRECOND_NET) return fail_arg("unknown precond");
+  const bool use_net = prm.precond == STAG_PRECOND_NET;
+  if (use_net) {
+    if (nprob != 1) return fail_arg("the network preconditioner solves one problem at a time");
+    if (!prm.net) return fail_arg("precond = STAG_PRECOND_NET needs a network");
+    if (net_lattice(prm.net) != probs[0].lat) return fail_arg("the network was built on another lattice");
+    if (!(prm.stall_ratio > 0.0)) return fail_arg("stall_ratio must be positive");
+  }
   if (prm.check_interval <= 0) prm.check_interval = 16;
   if (prm.reliable_interval <= 0) prm.reliable_interval = 50;
   if (prm.max_restarts < 0) prm.max_restarts = 0;
@@ -162,6 +273,13 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     if (mixed) {
       STAG_HIP_TRY(L->vec[V_RL].ensure(spinor_field_bytes(L, P, n)));
       STAG_HIP_TRY(L->vec[V_XL].ensure(spinor_field_bytes(L, P32, n)));
+    }
+    if (use_net) {
+      // flexible CG keeps d and Ad in FP64 whatever the inner precision of the plain-CG phase
+      STAG_HIP_TRY(L->vec[V_Z].ensure(spinor_field_bytes(L, P64, n)));
+      STAG_HIP_TRY(L->vec[V_D].ensure(spinor_field_bytes(L, P64, n)));
+      STAG_HIP_TRY(L->vec[V_AD].ensure(spinor_field_bytes(L, P64, n)));
+      STAG_HIP_TRY(L->vec[V_T].ensure(spinor_field_bytes(L, P64, n)));
     }
     ProbDev pd = prob_dev(L, n, slot);
     for (int v = 0; v < kNumVec; ++v) pd.vec[v] = L->vec[v].ptr;
@@ -239,6 +357,12 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
 
   // ---- restart loop: r = b - M x (FP64), decide, iterate ----
   STAG_HIP_TRY(true_residual(R, 0));
+  std::vector<int> fell_back(nslots, 0);
+  if (use_net) {
+    stag_status fs = fcg_phase(R, prm, probs[0], d_hist, iters, fell_back);
+    if (fs != STAG_OK) return fs;
+    STAG_HIP_TRY(true_residual(R, 0));
+  }
   const int x_prec = mixed ? P32 : P64;
   const int x_id = mixed ? V_XL : V_X;
   std::vector<int> done_status(nslots, STAG_OK);
@@ -391,6 +515,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     o.iters = iters[s];
     o.restarts = std::max(0, passes[s] - 1);
     o.n_reliable = n_rel[s];
+    o.fell_back = fell_back[s];
     o.true_resid = R.h_scal[s].aux;
     o.converged = done_status[s] == STAG_OK;
     o.status = done_status[s];

@@ -46,6 +46,8 @@ struct Scal {
   double aux;        // scratch scalar (true residual, stall monitor)
   double rel_thr;    // mixed precision: r^dag r below which a reliable update is due
   double cre, cim;   // mixed precision: d += (cre + i cim) r after a reliable update
+  double ar, ai;     // flexible CG: complex alpha = <d, r> / <d, A d>
+  double br, bi;     // flexible CG: complex beta = -<A d_prev, z> / <d_prev, A d_prev>
   int state;
   int iter;          // iterations since the last (re)start
   int max_iter;
@@ -55,7 +57,7 @@ struct Scal {
 };
 static_assert(sizeof(Scal) % 8 == 0, "Scal alignment");
 
-enum ScalFlags : int { kFlagNaN = 1, kFlagMaxIter = 2, kFlagRelDue = 4 };
+enum ScalFlags : int { kFlagNaN = 1, kFlagMaxIter = 2, kFlagRelDue = 4, kFlagBreakdown = 8 };
 
 // Vector roles in a solver workspace (one [nrhs][V/2][3] array per role and problem).
 enum VecId : int {

@@ -12,9 +12,10 @@ from typing import Iterable, Sequence
 import torch
 
 from . import _lib
-from ._lib import PREC, StagError, StagInfo, StagParams, StagProblem, StagShape, check, lib
+from ._lib import (PREC, StagError, StagInfo, StagParams, StagProblem, StagShape, StagTrainInfo, StagTrainParams,
+                   check, lib)
 
-__all__ = ["Lattice", "cg_solve_batch", "StagError", "solve_params", "tune_cache_save", "tune_cache_load"]
+__all__ = ["Lattice", "Net", "cg_solve_batch", "StagError", "solve_params", "tune_cache_save", "tune_cache_load"]
 
 
 def _stream(stream=None) -> int:
@@ -38,7 +39,7 @@ def _dev_tensor(t: torch.Tensor, name: str, shape_tail=None) -> torch.Tensor:
 
 def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliable_delta=0.1, check_interval=16,
                  max_restarts=5, profile=False, history_len=0, history=None, stall_window=10,
-                 stall_ratio=0.9, autotune=False) -> StagParams:
+                 stall_ratio=0.9, autotune=False, net=None) -> StagParams:
     p = _lib.default_params()
     p.tol = tol
     p.prec = PREC[prec]
@@ -54,6 +55,9 @@ def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliab
     p.stall_window = stall_window
     p.stall_ratio = stall_ratio
     p.autotune = 1 if autotune else 0
+    if net is not None:
+        p.precond = 1
+        p.net = net.handle
     return p
 
 
@@ -188,3 +192,95 @@ def cg_solve_batch(problems, raise_on_fail=True, stream=None, **params):
     if raise_on_fail:
         check(st, "stag_cg_solve_batch")
     return xs, [i.as_dict() for i in infos]
+
+
+class Net:
+    """The gauge-covariant network preconditioner on a lattice (its FP32 links must be loaded)."""
+
+    def __init__(self, lat: Lattice, layers: int = 4, channels: int = 8, seed: int = 0):
+        h = C.c_void_p()
+        check(lib().stag_net_create(lat.handle, int(layers), int(channels), int(seed), C.byref(h)), "stag_net_create")
+        self._h = h
+        self.lat = lat
+        self.layers = layers
+        self.channels = channels
+        self.ch = [1] + [channels] * (layers - 1) + [1] if layers > 1 else [1, 1]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            check(lib().stag_net_destroy(self._h), "stag_net_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_weights(self) -> int:
+        n = C.c_int64()
+        check(lib().stag_net_num_weights(self._h, C.byref(n)), "stag_net_num_weights")
+        return n.value
+
+    def _flat(self, weights):
+        import numpy as np
+
+        flat = np.concatenate([np.asarray(w, dtype=np.complex128).reshape(-1) for w in weights])
+        return np.ascontiguousarray(flat.view(np.float64))
+
+    def _split(self, flat):
+        import numpy as np
+
+        z = flat.view(np.complex128)
+        out, k = [], 0
+        for ci, co in zip(self.ch[:-1], self.ch[1:]):
+            n = 9 * co * ci
+            out.append(z[k:k + n].reshape(9, co, ci).copy())
+            k += n
+        return out
+
+    def set_weights(self, weights):
+        flat = self._flat(weights)
+        check(lib().stag_net_set_weights(self._h, flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size // 2),
+              "stag_net_set_weights")
+
+    def get_weights(self):
+        import numpy as np
+
+        flat = np.zeros(2 * self.num_weights())
+        check(lib().stag_net_get_weights(self._h, flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size // 2),
+              "stag_net_get_weights")
+        return self._split(flat)
+
+    def apply(self, r: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        nrhs = self.lat._vec(r, "in")
+        out = torch.empty_like(r) if out is None else out
+        check(lib().stag_net_apply(self._h, r.data_ptr(), out.data_ptr(), nrhs, _stream(stream)), "stag_net_apply")
+        return out
+
+    def loss_grad(self, b: torch.Tensor, x: torch.Tensor, stream=None):
+        import numpy as np
+
+        n = self.lat._vec(b, "b")
+        self.lat._vec(x, "x")
+        loss = C.c_double()
+        g = np.zeros(2 * self.num_weights())
+        check(lib().stag_net_loss_grad(self._h, b.data_ptr(), x.data_ptr(), n, C.byref(loss),
+                                       g.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)), "stag_net_loss_grad")
+        return loss.value, self._split(g)
+
+    def train(self, b: torch.Tensor, x: torch.Tensor, epochs=10, batch=8, lr=1e-3, seed=1, stream=None) -> dict:
+        n = self.lat._vec(b, "b")
+        self.lat._vec(x, "x")
+        p = StagTrainParams()
+        lib().stag_train_params_default(C.byref(p))
+        p.epochs, p.batch, p.lr, p.seed = int(epochs), int(batch), float(lr), int(seed)
+        info = StagTrainInfo()
+        check(lib().stag_net_train(self._h, b.data_ptr(), x.data_ptr(), n, C.byref(p), C.byref(info),
+                                   _stream(stream)), "stag_net_train")
+        return {k: getattr(info, k) for k, _ in info._fields_}

@@ -49,7 +49,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler on this host")
-    mirrors = {"stag_cg_params": _lib.StagParams, "stag_cg_info": _lib.StagInfo, "stag_problem": _lib.StagProblem}
+    mirrors = {"stag_cg_params": _lib.StagParams, "stag_cg_info": _lib.StagInfo, "stag_problem": _lib.StagProblem,
+               "stag_shape": _lib.StagShape, "stag_train_params": _lib.StagTrainParams,
+               "stag_train_info": _lib.StagTrainInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "stagcg.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
@@ -131,3 +133,12 @@ def test_tune_cache_roundtrip(lib, tmp_path):
 def test_shape_arguments_validated(lib):
     assert lib.stag_set_dslash_shape(None, 0, 1, 256, 1) == 1
     assert lib.stag_tune_dslash(None, 0, 1, None, None, 0, None, None) == 1
+
+
+def test_network_arguments_validated(lib):
+    h = C.c_void_p()
+    assert lib.stag_net_create(None, 4, 8, 0, C.byref(h)) == 1
+    assert lib.stag_net_destroy(None) == 1
+    assert lib.stag_net_apply(None, None, None, 1, None) == 1
+    assert lib.stag_net_num_weights(None, None) == 1
+    assert lib.stag_net_train(None, None, None, 1, None, None, None) == 1

@@ -1,0 +1,119 @@
+"""GPU parity of the network preconditioner and of flexible CG against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import quant
+from oracle.cg import true_residual
+from oracle.dslash import apply_m
+from oracle.net import folded_fat, init_weights, loss_and_grads, net_forward
+from stag_inputs import fat_field, gaussian_source, random_su3_field
+
+pytestmark = pytest.mark.gpu
+NAIK = -1.0 / 24.0
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def setup(dims, seed):
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    fat, lng = fat_field(dims, seed), random_su3_field(dims, seed + 1)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32"))
+    return lat, fat, lng
+
+
+@pytest.mark.parametrize("dims,channels", [((4, 4, 4, 8), [1, 4, 4, 1]), ((6, 4, 4, 6), [1, 8, 8, 8, 1]),
+                                           ((4, 2, 6, 4), [1, 2, 1]), ((4, 4, 4, 4), [1, 1])])
+def test_net_forward_matches_oracle(gpu_lib, dims, channels):
+    """FP32 network vs the FP64 oracle on FP32-rounded links and weights.
+
+    Each output is a sum over at most 9 directions x 8 channels x 3 colours of complex products per
+    layer, accumulated in binary32: with four layers the relative error stays below
+    4 x 216 x 2^-24 ~ 5e-5 in the worst case; 2e-5 normwise is the test bound."""
+    from paper_1010_4782_amd.stagcg import Net
+
+    print(f"net forward {dims} {channels}", flush=True)
+    lat, fat, _ = setup(dims, 3)
+    net = Net(lat, layers=len(channels) - 1, channels=max(channels[1:-1] or [1]))
+    W = init_weights(channels, 4, scale=1.0)
+    W32 = [quant.to_f32(w) for w in W]
+    net.set_weights(W32)
+    got = [g for g in net.get_weights()]
+    for a, b in zip(got, W32):
+        np.testing.assert_array_equal(a, b)
+    r = gaussian_source(dims, 5, 2)
+    out = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    Ft = quant.to_f32(folded_fat(fat, dims))
+    for k in range(2):
+        ref = net_forward(Ft, W32, quant.to_f32(r[k]), dims)
+        assert rel(out[k], ref) <= 2e-5
+
+
+def test_net_loss_and_gradients_match_oracle(gpu_lib):
+    from paper_1010_4782_amd.stagcg import Net
+
+    print("net loss/grad", flush=True)
+    dims = (4, 4, 2, 6)
+    lat, fat, _ = setup(dims, 7)
+    channels = [1, 4, 4, 1]
+    net = Net(lat, layers=3, channels=4)
+    W32 = [quant.to_f32(w) for w in init_weights(channels, 8, scale=1.0)]
+    net.set_weights(W32)
+    b = gaussian_source(dims, 9, 3)
+    x = gaussian_source(dims, 10, 3)
+    loss, grads = net.loss_grad(torch.from_numpy(b).cuda(), torch.from_numpy(x).cuda())
+    Ft = quant.to_f32(folded_fat(fat, dims))
+    L, G = loss_and_grads(Ft, W32, [(quant.to_f32(b[i]), x[i]) for i in range(3)], dims)
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    for g, gr in zip(grads, G):
+        assert rel(g, gr) <= 1e-4
+
+
+def test_fcg_identity_network_is_cg(gpu_lib):
+    """A one-layer network with W_0 = 1 is the identity: FCG then follows plain CG."""
+    from paper_1010_4782_amd.stagcg import Net
+
+    print("fcg identity", flush=True)
+    dims = (8, 8, 8, 8)
+    lat, fat, lng = setup(dims, 11)
+    net = Net(lat, layers=1, channels=1)
+    W = np.zeros((9, 1, 1), complex)
+    W[0, 0, 0] = 1.0
+    net.set_weights([W])
+    m = 0.05
+    b = gaussian_source(dims, 12)
+    bt = torch.from_numpy(b).cuda()
+    x0, i0 = lat.cg_solve(bt, m)
+    x1, i1 = lat.cg_solve(bt, m, net=net, stall_window=10)
+    assert i1[0]["converged"] == 1 and i1[0]["fell_back"] == 0
+    assert abs(i1[0]["iters"] - i0[0]["iters"]) <= max(5, 0.05 * i0[0]["iters"])
+    assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[0], x1.cpu().numpy()[0]) <= 1.05e-10
+
+
+def test_fcg_trained_network_and_forced_fallback(gpu_lib):
+    """Train on solver-made pairs; FCG with the network reaches the true residual; a stall threshold
+    that no progress can meet forces the plain-CG fallback, which still converges."""
+    from paper_1010_4782_amd.stagcg import Net
+
+    print("fcg trained + fallback", flush=True)
+    dims = (8, 8, 8, 8)
+    lat, fat, lng = setup(dims, 13)
+    m = 0.05
+    bs = torch.from_numpy(gaussian_source(dims, 14, 16)).cuda()
+    xs, _ = lat.cg_solve(bs, m)
+    net = Net(lat, layers=4, channels=4, seed=3)
+    info = net.train(bs, xs, epochs=6, batch=4, lr=3e-3)
+    assert info["loss_last"] < info["loss_first"]
+    b = gaussian_source(dims, 15)
+    bt = torch.from_numpy(b).cuda()
+    A = lambda v: apply_m(fat, lng, v, dims, m)
+    x1, i1 = lat.cg_solve(bt, m, net=net, stall_window=10)
+    assert i1[0]["converged"] == 1
+    assert true_residual(A, b[0], x1.cpu().numpy()[0]) <= 1.05e-10
+    x2, i2 = lat.cg_solve(bt, m, net=net, stall_window=5, stall_ratio=1e-30)
+    assert i2[0]["fell_back"] == 1 and i2[0]["converged"] == 1
+    assert true_residual(A, b[0], x2.cpu().numpy()[0]) <= 1.05e-10
