@@ -100,6 +100,80 @@ def measured_traffic(prec: str, dims):
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def run_learned_preconditioner(a, out_json):
+    """Workload 4: train the network on (b, x = M^-1 b) pairs made by the batched FP64 solver, then time
+    flexible CG with it against plain FP64 CG and mixed-precision CG on the workload's source."""
+    import torch
+
+    from paper_1010_4782_amd.stagcg import Lattice, Net
+    from stag_inputs import WORKLOADS, gaussian_source_device, workload_links, workload_sources
+
+    w = WORKLOADS[4]
+    dims, _ = w["lattices"][0]
+    mass, tol = w["masses"][0], w["tol"]
+    npairs = a.train_pairs if a.train_pairs > 0 else w["train_pairs"]
+    fat, lng = workload_links(4)
+    b_eval = torch.from_numpy(workload_sources(4)).cuda()
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0,
+                   precs=("f64", "f32", a.prec))
+    del fat, lng
+    half = lat.half
+    chunk = 8
+    bs = torch.empty((npairs, half, 3), dtype=torch.complex128, device="cuda")
+    xs = torch.empty_like(bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c0 in range(0, npairs, chunk):
+        n = min(chunk, npairs - c0)
+        bs[c0:c0 + n] = gaussian_source_device(dims, 4000 + c0, n)
+        x, _ = lat.cg_solve(bs[c0:c0 + n].contiguous(), mass, tol=tol, autotune=True)
+        xs[c0:c0 + n] = x
+        if (c0 // chunk) % 25 == 0:
+            print(f"# training data {c0 + n}/{npairs}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = Net(lat, layers=w["layers"], channels=w["channels"], seed=1, hermitian=True)
+    t0 = time.perf_counter()
+    tinfo = net.train(bs, xs, epochs=a.epochs, batch=8, lr=a.lr, loss=a.loss, mass=mass)
+    t_train = time.perf_counter() - t0
+    print(f"# trained: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} in {t_train:.1f} s",
+          file=sys.stderr, flush=True)
+    del bs, xs
+    res = {}
+    for name, kw in (("fcg_net", dict(net=net, stall_window=10)), ("fp64_cg", {}),
+                     ("mixed_" + a.prec, dict(prec=a.prec))):
+        lat.cg_solve(b_eval, mass, tol=tol, autotune=True, **kw)  # warm-up (and tuning)
+        times = []
+        for _ in range(max(1, a.steps)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, info = lat.cg_solve(b_eval, mass, tol=tol, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+        res[name] = {"s": min(times), "iters": info[0]["iters"], "true_resid": info[0]["true_resid"],
+                     "fell_back": info[0]["fell_back"]}
+        print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        net.apply(b_eval)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - t1) / 20
+    out = {"metric": METRIC, "value": res["fcg_net"]["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
+           "ms_per_step": 1e3 * res["fcg_net"]["s"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (network f32)", "data": "synthetic",
+           "config": {"workload": f"{dims[0]}^3x{dims[3]}, m={mass}, flexible CG with a {w['layers']}-layer, "
+                                  f"{w['channels']}-channel gauge-covariant network vs plain CG, true residual {tol}",
+                      "train_pairs": npairs, "epochs": a.epochs, "loss": a.loss},
+           "solves": res, "speedup_fcg_vs_fp64_cg": res["fp64_cg"]["s"] / res["fcg_net"]["s"],
+           "network_apply_ms": 1e3 * t_apply, "training": {"data_s": t_data, "train_s": t_train, **tinfo}}
+    saved = res["fp64_cg"]["s"] - res["fcg_net"]["s"]
+    out["break_even_solves"] = (t_data + t_train) / saved if saved > 0 else None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,11 +185,18 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap the inner iterations (for counter-collection runs; the solve then stops early)")
+    ap.add_argument("--train-pairs", type=int, default=0, help="workload 4: training pairs (0: the workload's 2000)")
+    ap.add_argument("--epochs", type=int, default=5, help="workload 4: training epochs")
+    ap.add_argument("--lr", type=float, default=2e-3, help="workload 4: Adam step size")
+    ap.add_argument("--loss", default="residual", choices=["residual", "solution"], help="workload 4: training loss")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU runs are not supported.",
               file=sys.stderr)
         return 2
+
+    if a.workload == 4:
+        return run_learned_preconditioner(a, None)
 
     import numpy as np
     import torch

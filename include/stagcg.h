@@ -196,17 +196,28 @@ stag_status stag_tune_cache_load(const char* path);
  * The network needs the lattice's FP32 links (stag_load_links with STAG_PREC_BIT(STAG_F32)); it keeps
  * pointers into them, so reload links only with the same lattice and destroy nets before the lattice.
  * channels: 1, 2, 4 or 8; layers in [1, 16]; seed: initial weights. */
-stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint64_t seed, stag_net_t* out);
+#define STAG_NET_HERMITIAN 1u  /* tie the second half of the layers to the adjoints of the first half in reverse
+                                  order, N = K^dag K: Hermitian positive semi-definite, as CG needs of a
+                                  preconditioner (layers must be even) */
+stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint32_t flags, uint64_t seed,
+                            stag_net_t* out);
 stag_status stag_net_destroy(stag_net_t net);
 stag_status stag_net_num_weights(stag_net_t net, int64_t* n_complex);
+/* set: with STAG_NET_HERMITIAN the second half of the layers is rederived from the first half. */
 stag_status stag_net_set_weights(stag_net_t net, const double* w, int64_t n_complex);   /* host complex128 */
 stag_status stag_net_get_weights(stag_net_t net, double* w, int64_t n_complex);
 /* out = N(in) for nrhs even-site vectors: device complex128 [nrhs][V/2][3]; in and out must not overlap. */
 stag_status stag_net_apply(stag_net_t net, const void* in, void* out, int32_t nrhs, void* stream);
-/* Loss L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2 over npairs pairs (device complex128 [npairs][V/2][3] each)
- * and, if grad is not NULL, dL/dconj(W) in the weight layout (host complex128).  Synchronises. */
-stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, double* loss,
-                               double* grad, void* stream);
+/* Training losses over pairs (b_i, x_i = M^{-1} b_i) (gradients are per layer, every layer's weights
+ * treated as independent; the trainer adds the tied layers' gradients):
+ *   loss_kind 0 (solution):  L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2
+ *   loss_kind 1 (residual):  L = sum_i ||M (N(b_i) - x_i)||^2 / ||b_i||^2 = sum_i ||M N(b_i) - b_i||^2 / ||b_i||^2,
+ *                            M = 4 mass^2 - D_eo D_oe applied in FP64 (weights the modes a local
+ *                            network can represent; kind 0 is dominated by the lowest modes).
+ * stag_net_loss_grad returns L and, if grad is not NULL, dL/dconj(W) in the weight layout (host
+ * complex128); b, x: device complex128 [npairs][V/2][3].  Synchronises. */
+stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, int32_t loss_kind,
+                               double mass, double* loss, double* grad, void* stream);
 
 typedef struct {
   int32_t epochs;            /* passes over the training pairs (default 10) */
@@ -214,7 +225,10 @@ typedef struct {
   double lr;                 /* Adam step size (default 1e-3) */
   double beta1, beta2, eps;  /* Adam moments (0.9, 0.999, 1e-8) */
   uint64_t seed;             /* shuffling of the pairs (default 1) */
-  int32_t reserved[8];
+  int32_t loss_kind;         /* 0: solution error, 1: residual (see stag_net_loss_grad; default 1) */
+  int32_t reserved0;
+  double mass;               /* mass of M for loss_kind 1 */
+  int32_t reserved[6];
 } stag_train_params;
 
 typedef struct {

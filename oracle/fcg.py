@@ -14,8 +14,11 @@ beta_k = <z_k, r_k - r_{k-1}> / <z_{k-1}, r_{k-1}> is equal in exact arithmetic 
 lost 40% in iterations to CG with N = identity in double precision, so the
 explicit orthogonalisation is used.
 
-Fallback: if ||r_k|| > stall_ratio * ||r_{k-w}|| for the stall window w, the
-preconditioner is abandoned and plain CG (oracle.cg) finishes from the current x.
+Fallback: every w iterations (the stall window) the smallest ||r|| seen so far is
+compared with the smallest one seen w iterations earlier; if it did not fall below
+stall_ratio times that value, the preconditioner is abandoned and plain CG
+(oracle.cg) finishes from the current x.  (The residual of a preconditioned CG need
+not fall monotonically, so the running minimum is compared, not ||r_k||.)
 The result is judged, like every solve, by its true residual.
 """
 from __future__ import annotations
@@ -62,7 +65,7 @@ def fcg(apply_a, precond, b, tol=1e-10, x0=None, max_iter=None, stall_window=10,
         res.resid_history.append(norms[-1] / np.sqrt(b2))
         if norms[-1] ** 2 <= tol * tol * b2:
             break
-        if k >= stall_window and norms[-1] > stall_ratio * norms[-1 - stall_window]:
+        if k % stall_window == 0 and min(norms) > stall_ratio * min(norms[:len(norms) - stall_window]):
             res.fell_back = True
             break
         z = precond(r)

@@ -95,16 +95,29 @@ def net_backward(Ft, weights, acts, g_out_e, dims):
     return grads
 
 
-def loss_and_grads(Ft, weights, pairs, dims):
-    """L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2 and dL/d conj(W) per layer."""
+def loss_and_grads(Ft, weights, pairs, dims, apply_m=None):
+    """Training loss and dL/d conj(W) per layer.
+
+    apply_m None (solution loss): L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2, output gradient (N(b) - x)/||x||^2.
+    apply_m given (residual loss): L = sum_i ||M N(b_i) - b_i||^2 / ||b_i||^2 (equal to
+    ||M (N(b_i) - x_i)||^2 / ||b_i||^2 for exact pairs); M is Hermitian, so the output gradient is
+    M (M N(b) - b) / ||b||^2.
+    """
     total = 0.0
     grads = [np.zeros_like(W) for W in weights]
     for b, x in pairs:
         out, acts = net_forward(Ft, weights, b, dims, keep=True)
-        nx = float(np.vdot(x, x).real)
-        res = out - x
-        total += float(np.vdot(res, res).real) / nx
-        for acc, gl in zip(grads, net_backward(Ft, weights, acts, res / nx, dims)):
+        if apply_m is None:
+            nx = float(np.vdot(x, x).real)
+            res = out - x
+            total += float(np.vdot(res, res).real) / nx
+            g = res / nx
+        else:
+            nb = float(np.vdot(b, b).real)
+            res = apply_m(out) - b
+            total += float(np.vdot(res, res).real) / nb
+            g = apply_m(res) / nb
+        for acc, gl in zip(grads, net_backward(Ft, weights, acts, g, dims)):
             acc += gl
     return total, grads
 
@@ -117,3 +130,17 @@ def init_weights(channels, seed: int, scale: float = 0.1):
         s = scale / np.sqrt(NDIR * cin)
         out.append(s * (rng.standard_normal((NDIR, cout, cin)) + 1j * rng.standard_normal((NDIR, cout, cin))))
     return out
+
+
+def adjoint_layer_weights(W):
+    """Weights of the adjoint layer: adj(W)[d'][a][b] = conj(W[d][b][a]), d' the opposite direction."""
+    opp = [0, 5, 6, 7, 8, 1, 2, 3, 4]
+    A = np.empty((9, W.shape[2], W.shape[1]), dtype=W.dtype)
+    for d in range(9):
+        A[opp[d]] = W[d].conj().T
+    return A
+
+
+def hermitian_weights(K):
+    """Layers of N = K^dag K: the layers of K followed by their adjoints in reverse order."""
+    return list(K) + [adjoint_layer_weights(W) for W in reversed(K)]

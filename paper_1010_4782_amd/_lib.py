@@ -92,7 +92,10 @@ class StagTrainParams(C.Structure):
         ("beta2", C.c_double),
         ("eps", C.c_double),
         ("seed", C.c_uint64),
-        ("reserved", C.c_int32 * 8),
+        ("loss_kind", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("mass", C.c_double),
+        ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -125,14 +128,15 @@ SIGNATURES = {
     "stag_set_dslash_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "stag_tune_cache_save": (C.c_int, [C.c_char_p]),
     "stag_tune_cache_load": (C.c_int, [C.c_char_p]),
-    "stag_net_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "stag_net_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64,
+                                  C.POINTER(C.c_void_p)]),
     "stag_net_destroy": (C.c_int, [C.c_void_p]),
     "stag_net_num_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "stag_net_set_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
     "stag_net_get_weights": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
     "stag_net_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
-    "stag_net_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
-                                     C.POINTER(C.c_double), C.c_void_p]),
+    "stag_net_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "stag_train_params_default": (None, [C.POINTER(StagTrainParams)]),
     "stag_net_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(StagTrainParams),
                                  C.POINTER(StagTrainInfo), C.c_void_p]),

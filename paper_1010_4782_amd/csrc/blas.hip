@@ -293,16 +293,17 @@ __global__ __launch_bounds__(kMaxWG) void k_fcg_beta_dot(Batch B, int gate) {
 
 // One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.
 __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
-                                                  double* hist, int hist_stride) {
+                                                  int aux_wg, double* hist, int hist_stride) {
   __shared__ double lds[12];
   const int slot = blockIdx.x;
   int p = 0;
   while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
   if (!slot_on(B.scal, slot, gate)) return;
-  const int ntiles = ceil_div(B.probs[p].g.half, producer_wg);
   const int nk = (what == FIN_ORTHO || what == FIN_FCG_ALPHA) ? 3 : (what == FIN_FCG_BETA ? 2 : 1);
   double s[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < nk; ++k) {
+    // the first kind comes from a launch of producer_wg sites per block, the others from aux_wg
+    const int ntiles = ceil_div(B.probs[p].g.half, k == 0 ? producer_wg : aux_wg);
     const double* src = B.partial + ((long)slot * kPartialSlots + kind + k) * B.pstride;
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s[k] += src[i];
   }
@@ -391,6 +392,7 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
       }
       sc.delta_old = sc.delta;
       sc.delta = sum;
+      sc.dmin = fmin(sc.dmin, sum);
       sc.iter += 1;
       if (sum <= sc.thr) sc.state = 1;
       if (sc.iter >= sc.max_iter) {
@@ -532,10 +534,11 @@ hipError_t launch_zero_vec(const BatchHost& bh, int prec, int v_id, int gate, in
 }
 
 hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, int producer_wg, double* hist,
-                           int hist_stride, hipStream_t st) {
+                           int hist_stride, hipStream_t st, int aux_wg) {
   if (bh.nslots == 0) return hipSuccess;
   const Batch B = make_batch(bh, producer_wg, 1);
-  k_finalize<<<bh.nslots, 256, 0, st>>>(B, what, kind, gate, producer_wg, hist, hist_stride);
+  k_finalize<<<bh.nslots, 256, 0, st>>>(B, what, kind, gate, producer_wg, aux_wg > 0 ? aux_wg : producer_wg, hist,
+                                        hist_stride);
   return hipGetLastError();
 }
 

@@ -39,8 +39,10 @@ hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, in
 
 // Vector stages of the solvers (every one is one launch over all slots of the batch).
 hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st);
+// producer_wg: sites per block of the launch that wrote the first partial kind; aux_wg (0: the same)
+// for the further kinds of multi-kind modes.
 hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, int producer_wg, double* hist,
-                           int hist_stride, hipStream_t st);
+                           int hist_stride, hipStream_t st, int aux_wg = 0);
 hipError_t launch_update_r(const BatchHost& bh, int prec, int wg, hipStream_t st);
 hipError_t launch_update_xd(const BatchHost& bh, int prec, int x_prec, int x_id, int wg, hipStream_t st);
 hipError_t launch_copy_vec(const BatchHost& bh, int src_prec, int src_id, int dst_prec, int dst_id, int gate,

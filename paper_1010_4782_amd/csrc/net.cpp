@@ -18,6 +18,7 @@ struct stag_net_s {
   stag_lattice_s* lat = nullptr;
   int layers = 0;
   int channels = 0;
+  bool herm = false;                         // second half of the layers = adjoints of the first half
   std::vector<int> ch;                       // ch[0] = 1, ch[L] = 1
   std::vector<std::vector<cplx>> w;          // per layer [9][cout][cin]
   stag::DevBuf wdev;                         // complex64 weights of all layers, then their adjoints
@@ -28,6 +29,7 @@ struct stag_net_s {
   stag::DevBuf partial;                      // weight-gradient partials
   stag::DevBuf gacc;                         // accumulated weight gradients, complex128, all layers
   stag::DevBuf lossbuf;                      // per-pair losses and norms
+  stag::DevBuf vy, vt, vu;                   // FP64 even-site vectors of the residual loss
   std::vector<std::vector<double>> am, av;   // Adam moments per layer (re, im interleaved)
   long adam_t = 0;
   ~stag_net_s() {
@@ -39,6 +41,9 @@ struct stag_net_s {
     partial.release();
     gacc.release();
     lossbuf.release();
+    vy.release();
+    vt.release();
+    vu.release();
   }
 };
 
@@ -47,6 +52,23 @@ namespace stag {
 namespace {
 
 constexpr int kWgradBlocks = 240;
+
+// adj(W)[d'][a][b] = conj(W[d][b][a]) with d' the opposite direction: the weights of the adjoint layer.
+std::vector<cplx> adjoint_weights(const std::vector<cplx>& W, int ci, int co) {
+  std::vector<cplx> A(W.size());
+  for (int d = 0; d < 9; ++d) {
+    const int dp = d == 0 ? 0 : (d <= 4 ? d + 4 : d - 4);
+    for (int a = 0; a < ci; ++a)
+      for (int b = 0; b < co; ++b) A[(dp * ci + a) * co + b] = std::conj(W[(d * co + b) * ci + a]);
+  }
+  return A;
+}
+
+void tie_weights(stag_net_s* n) {
+  if (!n->herm) return;
+  for (int l = 0; l < n->layers / 2; ++l)
+    n->w[n->layers - 1 - l] = adjoint_weights(n->w[l], n->ch[l], n->ch[l + 1]);
+}
 
 int nweights(const stag_net_s* n, int l) { return 9 * n->ch[l] * n->ch[l + 1]; }
 
@@ -77,16 +99,9 @@ hipError_t upload_weights(stag_net_s* n, hipStream_t st) {
   }
   for (int l = 0; l < n->layers; ++l) {
     n->aoff[l] = off;
-    const int ci = n->ch[l], co = n->ch[l + 1];
-    // adjoint layer: direction d' = opposite(d), weights W_d^H ([ci][co])
-    for (int d = 0; d < 9; ++d) {
-      const int dp = d == 0 ? 0 : (d <= 4 ? d + 4 : d - 4);
-      for (int a = 0; a < ci; ++a)
-        for (int b = 0; b < co; ++b) {
-          const cplx v = std::conj(n->w[l][(d * co + b) * ci + a]);
-          h[off + (dp * ci + a) * co + b] = make_float2((float)v.real(), (float)v.imag());
-        }
-    }
+    // adjoint layer (used by the backward pass): direction d' = opposite(d), weights W_d^H ([ci][co])
+    const std::vector<cplx> A = adjoint_weights(n->w[l], n->ch[l], n->ch[l + 1]);
+    for (int i = 0; i < nweights(n, l); ++i) h[off + i] = make_float2((float)A[i].real(), (float)A[i].imag());
     off += nweights(n, l);
   }
   hipError_t e = n->wdev.ensure(total * sizeof(float2));
@@ -135,17 +150,29 @@ hipError_t net_forward(stag_net_s* n, const void* in, void* out, hipStream_t st)
 }
 
 // Loss and weight gradients of one pair, accumulated into n->gacc (complex128 dL/dconj W); loss to *loss_dev.
-hipError_t net_backward_pair(stag_net_s* n, const void* b, const void* x, double inv_nx, double* loss_dev,
-                             hipStream_t st) {
+// Output gradient of the loss for one pair and the unscaled loss numerator in *loss_dev:
+//   kind 0: g = (N(b) - x) / |x|^2,            *loss_dev = |N(b) - x|^2            (inv = 1/|x|^2)
+//   kind 1: g = M (M N(b) - b) / |b|^2,        *loss_dev = |M N(b) - b|^2          (inv = 1/|b|^2)
+// (M Hermitian, so the gradient of |M y - b|^2 with respect to conj(y) is M (M y - b)).
+hipError_t net_backward_pair(stag_net_s* n, const void* b, const void* x, double inv, int kind, double mass,
+                             double* loss_dev, hipStream_t st) {
   const long half = n->lat->g.half;
-  hipError_t e = net_forward(n, b, nullptr, st);
+  hipError_t e = net_forward(n, b, kind == 1 ? n->vy.ptr : nullptr, st);
   if (e != hipSuccess) return e;
   int cur = 0;
   std::array<bool, 2> gnz = {true, false};
   double* part = reinterpret_cast<double*>(n->partial.ptr);
-  // *loss_dev = |N(b) - x|^2 (the caller scales it by 1 / |x|^2)
-  e = launch_net_loss(act_par(n, n->layers, 0), x, inv_nx, grad_par(n, cur, 1, 0), part, loss_dev, half, st);
-  if (e != hipSuccess) return e;
+  if (kind == 0) {
+    e = launch_net_loss(act_par(n, n->layers, 0), x, inv, grad_par(n, cur, 1, 0), part, loss_dev, half, st);
+    if (e != hipSuccess) return e;
+  } else {
+    if (stag_apply_m(n->lat, &mass, n->vy.ptr, n->vu.ptr, 1, st) != STAG_OK) return hipErrorUnknown;
+    e = launch_sub_norm(n->vu.ptr, b, n->vt.ptr, part, loss_dev, half, st);
+    if (e != hipSuccess) return e;
+    if (stag_apply_m(n->lat, &mass, n->vt.ptr, n->vu.ptr, 1, st) != STAG_OK) return hipErrorUnknown;
+    e = launch_scale_to_f32(n->vu.ptr, inv, grad_par(n, cur, 1, 0), half, st);
+    if (e != hipSuccess) return e;
+  }
   size_t goff = 0;
   std::vector<size_t> gofs(n->layers);
   for (int l = 0; l < n->layers; ++l) {
@@ -217,6 +244,10 @@ hipError_t net_alloc(stag_net_s* n) {
   if (e != hipSuccess) return e;
   e = n->gacc.ensure(net_grad_count(n) * sizeof(double));
   if (e != hipSuccess) return e;
+  e = n->vy.ensure(half * 48);
+  if (e == hipSuccess) e = n->vt.ensure(half * 48);
+  if (e == hipSuccess) e = n->vu.ensure(half * 48);
+  if (e != hipSuccess) return e;
   return n->lossbuf.ensure(64 * sizeof(double));
 }
 
@@ -231,8 +262,8 @@ void zero_adam(stag_net_s* n) {
 }
 
 // L = sum_i ||N(b_i) - x_i||^2 / ||x_i||^2 over the pairs idx; gradients accumulated in n->gacc.
-stag_status loss_grad(stag_net_s* n, const char* b, const char* x, const std::vector<int>& idx, double* loss,
-                      hipStream_t st) {
+stag_status loss_grad(stag_net_s* n, const char* b, const char* x, const std::vector<int>& idx, int kind,
+                      double mass, double* loss, hipStream_t st) {
   const long half = n->lat->g.half;
   const size_t vb = (size_t)half * 48;
   double* lb = reinterpret_cast<double*>(n->lossbuf.ptr);
@@ -240,14 +271,16 @@ stag_status loss_grad(stag_net_s* n, const char* b, const char* x, const std::ve
   double total = 0.0;
   for (int i : idx) {
     double nx = 0.0;
-    STAG_HIP_TRY(launch_norm2_c128(x + i * vb, part, lb + 8, half, st));
+    STAG_HIP_TRY(launch_norm2_c128((kind == 0 ? x : b) + i * vb, part, lb + 8, half, st));
     STAG_HIP_TRY(hipMemcpyAsync(&nx, lb + 8, sizeof(double), hipMemcpyDeviceToHost, st));
     STAG_HIP_TRY(hipStreamSynchronize(st));
     if (!(nx > 0.0)) {
-      set_error("a training solution x is zero");
+      set_error("a training vector (x for the solution loss, b for the residual loss) is zero");
       return STAG_ERR_ARG;
     }
-    STAG_HIP_TRY(net_backward_pair(n, b + i * vb, x + i * vb, 1.0 / nx, lb, st));
+    hipError_t e = net_backward_pair(n, b + i * vb, x + i * vb, 1.0 / nx, kind, mass, lb, st);
+    if (e == hipErrorUnknown) return STAG_ERR_HIP;  // stag_apply_m failed and set the message
+    STAG_HIP_TRY(e);
     double l2 = 0.0;
     STAG_HIP_TRY(hipMemcpyAsync(&l2, lb, sizeof(double), hipMemcpyDeviceToHost, st));
     STAG_HIP_TRY(hipStreamSynchronize(st));
@@ -261,11 +294,14 @@ stag_status loss_grad(stag_net_s* n, const char* b, const char* x, const std::ve
 
 extern "C" {
 
-stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint64_t seed, stag_net_t* out) {
+stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint32_t flags, uint64_t seed,
+                            stag_net_t* out) {
   try {
     if (!lat || !out) return net_arg("lattice and out must not be NULL");
     *out = nullptr;
     if (layers < 1 || layers > 16) return net_arg("layers must be in [1, 16]");
+    if (flags & ~STAG_NET_HERMITIAN) return net_arg("unknown network flags");
+    if ((flags & STAG_NET_HERMITIAN) && (layers % 2)) return net_arg("a Hermitian network needs an even layer count");
     if (channels != 1 && channels != 2 && channels != 4 && channels != 8) return net_arg("channels must be 1, 2, 4 or 8");
     if (!lat->loaded || !(lat->built & STAG_PREC_BIT(STAG_F32))) {
       set_error("the network transports need FP32 links: call stag_load_links with STAG_PREC_BIT(STAG_F32)");
@@ -275,6 +311,7 @@ stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels
     n->lat = lat;
     n->layers = layers;
     n->channels = channels;
+    n->herm = (flags & STAG_NET_HERMITIAN) != 0;
     n->ch.assign(layers + 1, channels);
     n->ch.front() = 1;
     n->ch.back() = 1;
@@ -286,6 +323,7 @@ stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels
       n->w[l].resize(9 * n->ch[l] * n->ch[l + 1]);
       for (auto& v : n->w[l]) v = cplx(s * nd(rng), s * nd(rng));
     }
+    tie_weights(n);
     hipError_t e = net_alloc(n);
     if (e == hipSuccess) e = upload_weights(n, nullptr);
     if (e != hipSuccess) {
@@ -329,6 +367,7 @@ stag_status stag_net_set_weights(stag_net_t net, const double* w, int64_t n_comp
       v = cplx(w[2 * k], w[2 * k + 1]);
       ++k;
     }
+  tie_weights(net);
   STAG_HIP_TRY(upload_weights(net, nullptr));
   zero_adam(net);
   return STAG_OK;
@@ -360,16 +399,19 @@ stag_status stag_net_apply(stag_net_t net, const void* in, void* out, int32_t nr
   return STAG_OK;
 }
 
-stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, double* loss,
-                               double* grad, void* stream) {
+stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, int32_t loss_kind,
+                               double mass, double* loss, double* grad, void* stream) {
   if (!net || !b || !x || !loss) return net_arg("network, b, x and loss must not be NULL");
   if (npairs < 1) return net_arg("npairs must be >= 1");
+  if (loss_kind != 0 && loss_kind != 1) return net_arg("loss_kind must be 0 or 1");
+  if (!std::isfinite(mass)) return net_arg("mass must be finite");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t ng = net_grad_count(net);
   STAG_HIP_TRY(hipMemsetAsync(net->gacc.ptr, 0, ng * sizeof(double), st));
   std::vector<int> idx(npairs);
   std::iota(idx.begin(), idx.end(), 0);
-  stag_status s = loss_grad(net, reinterpret_cast<const char*>(b), reinterpret_cast<const char*>(x), idx, loss, st);
+  stag_status s = loss_grad(net, reinterpret_cast<const char*>(b), reinterpret_cast<const char*>(x), idx, loss_kind,
+                            mass, loss, st);
   if (s != STAG_OK) return s;
   if (grad) {
     STAG_HIP_TRY(hipMemcpyAsync(grad, net->gacc.ptr, ng * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -388,6 +430,8 @@ void stag_train_params_default(stag_train_params* p) {
   p->beta2 = 0.999;
   p->eps = 1e-8;
   p->seed = 1;
+  p->loss_kind = 1;
+  p->mass = 0.0;
 }
 
 stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t npairs, const stag_train_params* prm_in,
@@ -398,7 +442,8 @@ stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t
   stag_train_params prm;
   if (prm_in) prm = *prm_in; else stag_train_params_default(&prm);
   if (prm.epochs < 1 || prm.batch < 1 || !(prm.lr > 0.0) || !(prm.beta1 >= 0.0 && prm.beta1 < 1.0) ||
-      !(prm.beta2 >= 0.0 && prm.beta2 < 1.0) || !(prm.eps > 0.0))
+      !(prm.beta2 >= 0.0 && prm.beta2 < 1.0) || !(prm.eps > 0.0) || (prm.loss_kind != 0 && prm.loss_kind != 1) ||
+      !std::isfinite(prm.mass))
     return net_arg("invalid training parameters");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t ng = net_grad_count(net);
@@ -415,17 +460,37 @@ stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t
       std::vector<int> idx(order.begin() + s0, order.begin() + std::min(npairs, s0 + prm.batch));
       STAG_HIP_TRY(hipMemsetAsync(net->gacc.ptr, 0, ng * sizeof(double), st));
       double l = 0.0;
-      stag_status s = loss_grad(net, reinterpret_cast<const char*>(b), reinterpret_cast<const char*>(x), idx, &l, st);
+      stag_status s = loss_grad(net, reinterpret_cast<const char*>(b), reinterpret_cast<const char*>(x), idx,
+                                prm.loss_kind, prm.mass, &l, st);
       if (s != STAG_OK) return s;
       ep_loss += l;
       STAG_HIP_TRY(hipMemcpyAsync(g.data(), net->gacc.ptr, ng * sizeof(double), hipMemcpyDeviceToHost, st));
       STAG_HIP_TRY(hipStreamSynchronize(st));
+      // tied layers: W_{L-1-l} = adj(W_l), so dL/dconj(W_l)[d][b][a] gains conj(dL/dconj(W_{L-1-l})[d'][a][b])
+      std::vector<size_t> goff(net->layers + 1, 0);
+      for (int li = 0; li < net->layers; ++li) goff[li + 1] = goff[li] + 2 * (size_t)nweights(net, li);
+      if (net->herm)
+        for (int li = 0; li < net->layers / 2; ++li) {
+          const int lt = net->layers - 1 - li;
+          const int ci = net->ch[li], co = net->ch[li + 1];
+          for (int d = 0; d < 9; ++d) {
+            const int dp = d == 0 ? 0 : (d <= 4 ? d + 4 : d - 4);
+            for (int b = 0; b < co; ++b)
+              for (int a = 0; a < ci; ++a) {
+                const size_t i0 = goff[li] + 2 * (size_t)((d * co + b) * ci + a);
+                const size_t i1 = goff[lt] + 2 * (size_t)((dp * ci + a) * co + b);
+                g[i0] += g[i1];
+                g[i0 + 1] -= g[i1 + 1];
+              }
+          }
+        }
       // Adam on (Re W, Im W): d L / d(Re, Im) = 2 (Re, Im) of d L / d conj W, averaged over the batch
       net->adam_t += 1;
       const double b1t = 1.0 - std::pow(prm.beta1, (double)net->adam_t);
       const double b2t = 1.0 - std::pow(prm.beta2, (double)net->adam_t);
-      size_t k = 0;
-      for (int li = 0; li < net->layers; ++li)
+      const int free_layers = net->herm ? net->layers / 2 : net->layers;
+      for (int li = 0; li < free_layers; ++li) {
+        size_t k = goff[li];
         for (size_t j = 0; j < net->w[li].size(); ++j) {
           double pr[2] = {net->w[li][j].real(), net->w[li][j].imag()};
           for (int c = 0; c < 2; ++c, ++k) {
@@ -438,6 +503,8 @@ stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t
           }
           net->w[li][j] = cplx(pr[0], pr[1]);
         }
+      }
+      tie_weights(net);
       STAG_HIP_TRY(upload_weights(net, st));
       ++steps;
     }

@@ -25,5 +25,8 @@ hipError_t launch_net_extract(const float2* in, void* out, long nsites, hipStrea
 hipError_t launch_net_loss(const float2* out, const void* x, double scale, float2* g, double* partial, double* sum,
                            long nsites, hipStream_t st);
 hipError_t launch_norm2_c128(const void* x, double* partial, double* sum, long nsites, hipStream_t st);
+hipError_t launch_sub_norm(const void* a, const void* b, void* out, double* partial, double* sum, long nsites,
+                           hipStream_t st);
+hipError_t launch_scale_to_f32(const void* in, double scale, float2* out, long nsites, hipStream_t st);
 
 }  // namespace stag

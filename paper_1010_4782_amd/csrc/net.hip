@@ -292,3 +292,49 @@ hipError_t launch_norm2_c128(const void* x, double* partial, double* sum, long n
 }
 
 }  // namespace stag
+
+namespace stag {
+
+// out = a - b (complex128), partial |out|^2 per block
+__global__ __launch_bounds__(256) void k_sub_norm(const double2* a, const double2* b, double2* out, double* partial,
+                                                  long n) {
+  __shared__ double lds[4];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s[1] = {0.0};
+  if (i < n) {
+    const double2 u = a[i], v = b[i];
+    const double2 w = make_double2(u.x - v.x, u.y - v.y);
+    out[i] = w;
+    s[0] = w.x * w.x + w.y * w.y;
+  }
+  block_sum<1>(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+// complex128 -> complex64 times a real scale
+__global__ __launch_bounds__(256) void k_scale_to_f32(const double2* in, double scale, float2* out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = in[i];
+  out[i] = make_float2((float)(scale * v.x), (float)(scale * v.y));
+}
+
+hipError_t launch_sub_norm(const void* a, const void* b, void* out, double* partial, double* sum, long nsites,
+                           hipStream_t st) {
+  const long n = nsites * 3;
+  const int nb = (int)((n + 255) / 256);
+  k_sub_norm<<<nb, 256, 0, st>>>(reinterpret_cast<const double2*>(a), reinterpret_cast<const double2*>(b),
+                                 reinterpret_cast<double2*>(out), partial, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum_partials<<<1, 256, 0, st>>>(partial, nb, sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(const void* in, double scale, float2* out, long nsites, hipStream_t st) {
+  const long n = nsites * 3;
+  k_scale_to_f32<<<(n + 255) / 256, 256, 0, st>>>(reinterpret_cast<const double2*>(in), scale, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace stag

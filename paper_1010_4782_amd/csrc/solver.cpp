@@ -134,6 +134,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     sc.iter = 0;
     sc.flags = 0;
     sc.br = sc.bi = 0.0;
+    sc.dmin = sc.delta;
     prev[s] = sc.delta;
     part[s] = 1;
     any = true;
@@ -162,7 +163,8 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
       if (e == hipSuccess)
         e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64.wg, R.shape64.r, R.st);
       if (e == hipSuccess) e = record(R);
-      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, R.shape64.wg, d_hist, R.hist_len, R.st);
+      if (e == hipSuccess)
+        e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, R.shape64.wg, d_hist, R.hist_len, R.st, kVecWG);
       if (e == hipSuccess) e = launch_fcg_update(R.bh, kVecWG, R.st);
       if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_RES, 1, 1, kVecWG, nullptr, 0, R.st);
       if (e == hipSuccess) e = apply_net();
@@ -179,11 +181,13 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
         if (sc.state == 2 && (sc.flags & kFlagBreakdown)) fell_back[s] = 1;
         continue;
       }
-      if (sc.delta > ratio2 * prev[s]) {
+      // the residual of a preconditioned CG need not fall monotonically: compare the best r^dag r
+      // of this window with the best one window earlier
+      if (sc.dmin > ratio2 * prev[s]) {
         fell_back[s] = 1;
         sc.state = 2;
       } else {
-        prev[s] = sc.delta;
+        prev[s] = sc.dmin;
         running = true;
       }
     }

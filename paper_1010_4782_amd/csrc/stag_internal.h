@@ -48,6 +48,7 @@ struct Scal {
   double cre, cim;   // mixed precision: d += (cre + i cim) r after a reliable update
   double ar, ai;     // flexible CG: complex alpha = <d, r> / <d, A d>
   double br, bi;     // flexible CG: complex beta = -<A d_prev, z> / <d_prev, A d_prev>
+  double dmin;       // flexible CG: smallest r^dag r seen (the stall test compares it window to window)
   int state;
   int iter;          // iterations since the last (re)start
   int max_iter;

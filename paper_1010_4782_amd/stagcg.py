@@ -197,9 +197,11 @@ def cg_solve_batch(problems, raise_on_fail=True, stream=None, **params):
 class Net:
     """The gauge-covariant network preconditioner on a lattice (its FP32 links must be loaded)."""
 
-    def __init__(self, lat: Lattice, layers: int = 4, channels: int = 8, seed: int = 0):
+    def __init__(self, lat: Lattice, layers: int = 4, channels: int = 8, seed: int = 0, hermitian: bool = False):
         h = C.c_void_p()
-        check(lib().stag_net_create(lat.handle, int(layers), int(channels), int(seed), C.byref(h)), "stag_net_create")
+        check(lib().stag_net_create(lat.handle, int(layers), int(channels), 1 if hermitian else 0, int(seed),
+                                    C.byref(h)), "stag_net_create")
+        self.hermitian = hermitian
         self._h = h
         self.lat = lat
         self.layers = layers
@@ -263,23 +265,28 @@ class Net:
         check(lib().stag_net_apply(self._h, r.data_ptr(), out.data_ptr(), nrhs, _stream(stream)), "stag_net_apply")
         return out
 
-    def loss_grad(self, b: torch.Tensor, x: torch.Tensor, stream=None):
+    LOSS = {"solution": 0, "residual": 1}
+
+    def loss_grad(self, b: torch.Tensor, x: torch.Tensor, loss="solution", mass=0.0, stream=None):
         import numpy as np
 
         n = self.lat._vec(b, "b")
         self.lat._vec(x, "x")
-        loss = C.c_double()
+        val = C.c_double()
         g = np.zeros(2 * self.num_weights())
-        check(lib().stag_net_loss_grad(self._h, b.data_ptr(), x.data_ptr(), n, C.byref(loss),
-                                       g.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)), "stag_net_loss_grad")
-        return loss.value, self._split(g)
+        check(lib().stag_net_loss_grad(self._h, b.data_ptr(), x.data_ptr(), n, self.LOSS[loss], float(mass),
+                                       C.byref(val), g.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)),
+              "stag_net_loss_grad")
+        return val.value, self._split(g)
 
-    def train(self, b: torch.Tensor, x: torch.Tensor, epochs=10, batch=8, lr=1e-3, seed=1, stream=None) -> dict:
+    def train(self, b: torch.Tensor, x: torch.Tensor, epochs=10, batch=8, lr=1e-3, seed=1, loss="residual", mass=0.0,
+              stream=None) -> dict:
         n = self.lat._vec(b, "b")
         self.lat._vec(x, "x")
         p = StagTrainParams()
         lib().stag_train_params_default(C.byref(p))
         p.epochs, p.batch, p.lr, p.seed = int(epochs), int(batch), float(lr), int(seed)
+        p.loss_kind, p.mass = self.LOSS[loss], float(mass)
         info = StagTrainInfo()
         check(lib().stag_net_train(self._h, b.data_ptr(), x.data_ptr(), n, C.byref(p), C.byref(info),
                                    _stream(stream)), "stag_net_train")

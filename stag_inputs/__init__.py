@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "GELL_MANN", "WORKLOADS", "su3_near_identity", "random_su3_field",
-    "fat_field", "gaussian_source", "gaussian_full_field", "random_gauge_transform",
+    "fat_field", "gaussian_source", "gaussian_source_device", "gaussian_full_field", "random_gauge_transform",
     "workload", "workload_links", "workload_sources", "half_volume", "volume",
 ]
 
@@ -127,6 +127,22 @@ def gaussian_source(dims, seed: int, nrhs: int = 1) -> np.ndarray:
     rng = np.random.default_rng(seed)
     shp = (nrhs, half_volume(dims), 3)
     return rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+
+
+def gaussian_source_device(dims, seed: int, nrhs: int, device="cuda"):
+    """Even-site Gaussian sources drawn on the GPU with a seeded torch generator, complex128
+    [nrhs][V/2][3]: the bulk training sources of the learned preconditioner (thousands of fields,
+    too many to draw on the host and copy).  Deterministic for a given seed, device type and
+    torch version."""
+    import torch
+
+    dims = _check_dims(dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    shp = (nrhs, half_volume(dims), 3)
+    re = torch.randn(shp, generator=g, dtype=torch.float64, device=device)
+    im = torch.randn(shp, generator=g, dtype=torch.float64, device=device)
+    return torch.complex(re, im)
 
 
 def gaussian_full_field(dims, seed: int) -> np.ndarray:

@@ -137,7 +137,7 @@ def test_shape_arguments_validated(lib):
 
 def test_network_arguments_validated(lib):
     h = C.c_void_p()
-    assert lib.stag_net_create(None, 4, 8, 0, C.byref(h)) == 1
+    assert lib.stag_net_create(None, 4, 8, 0, 0, C.byref(h)) == 1
     assert lib.stag_net_destroy(None) == 1
     assert lib.stag_net_apply(None, None, None, 1, None) == 1
     assert lib.stag_net_num_weights(None, None) == 1

@@ -73,6 +73,28 @@ def test_net_loss_and_gradients_match_oracle(gpu_lib):
         assert rel(g, gr) <= 1e-4
 
 
+def test_net_residual_loss_matches_oracle(gpu_lib):
+    from paper_1010_4782_amd.stagcg import Net
+
+    print("net residual loss/grad", flush=True)
+    dims = (4, 4, 2, 6)
+    lat, fat, lng = setup(dims, 17)
+    channels = [1, 2, 2, 1]
+    net = Net(lat, layers=3, channels=2)
+    W32 = [quant.to_f32(w) for w in init_weights(channels, 18, scale=1.0)]
+    net.set_weights(W32)
+    b = gaussian_source(dims, 19, 2)
+    m = 0.3
+    loss, grads = net.loss_grad(torch.from_numpy(b).cuda(), torch.from_numpy(b).cuda(), loss="residual", mass=m)
+    Ft = quant.to_f32(folded_fat(fat, dims))
+    A = lambda v: apply_m(fat, lng, v, dims, m)
+    # the network's FP32 output enters M in FP64 on both sides
+    L, G = loss_and_grads(Ft, W32, [(quant.to_f32(b[i]), None) for i in range(2)], dims, apply_m=A)
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    for g, gr in zip(grads, G):
+        assert rel(g, gr) <= 1e-4
+
+
 def test_fcg_identity_network_is_cg(gpu_lib):
     """A one-layer network with W_0 = 1 is the identity: FCG then follows plain CG."""
     from paper_1010_4782_amd.stagcg import Net
@@ -105,8 +127,12 @@ def test_fcg_trained_network_and_forced_fallback(gpu_lib):
     m = 0.05
     bs = torch.from_numpy(gaussian_source(dims, 14, 16)).cuda()
     xs, _ = lat.cg_solve(bs, m)
-    net = Net(lat, layers=4, channels=4, seed=3)
-    info = net.train(bs, xs, epochs=6, batch=4, lr=3e-3)
+    net = Net(lat, layers=4, channels=4, seed=3, hermitian=True)
+    info = net.train(bs, xs, epochs=6, batch=4, lr=3e-3, loss="residual", mass=m)
+    w = net.get_weights()
+    from oracle.net import hermitian_weights
+    for a, c in zip(w, hermitian_weights(w[:2])):
+        np.testing.assert_array_equal(a, c)
     assert info["loss_last"] < info["loss_first"]
     b = gaussian_source(dims, 15)
     bt = torch.from_numpy(b).cuda()
@@ -117,3 +143,20 @@ def test_fcg_trained_network_and_forced_fallback(gpu_lib):
     x2, i2 = lat.cg_solve(bt, m, net=net, stall_window=5, stall_ratio=1e-30)
     assert i2[0]["fell_back"] == 1 and i2[0]["converged"] == 1
     assert true_residual(A, b[0], x2.cpu().numpy()[0]) <= 1.05e-10
+
+
+def test_hermitian_network_on_gpu(gpu_lib):
+    """With tied weights the GPU network is Hermitian and positive to FP32 accuracy."""
+    from paper_1010_4782_amd.stagcg import Net
+
+    print("hermitian net", flush=True)
+    dims = (6, 4, 4, 6)
+    lat, fat, _ = setup(dims, 21)
+    net = Net(lat, layers=4, channels=8, seed=5, hermitian=True)
+    u = torch.from_numpy(gaussian_source(dims, 22)).cuda()
+    v = torch.from_numpy(gaussian_source(dims, 23)).cuda()
+    a = torch.vdot(u.flatten(), net.apply(v).flatten()).item()
+    b = torch.vdot(v.flatten(), net.apply(u).flatten()).item().conjugate()
+    assert abs(a - b) <= 1e-5 * abs(a)
+    q = torch.vdot(v.flatten(), net.apply(v).flatten()).item()
+    assert q.real > 0 and abs(q.imag) <= 1e-5 * q.real

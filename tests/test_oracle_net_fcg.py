@@ -6,8 +6,8 @@ from oracle import dense, geometry
 from oracle.cg import cg
 from oracle.dslash import apply_m, colour_rotate, gauge_transform_links
 from oracle.fcg import fcg
-from oracle.net import (folded_fat, init_weights, layer_backward, layer_forward, loss_and_grads, net_forward,
-                        transport, transport_adjoint)
+from oracle.net import (folded_fat, hermitian_weights, init_weights, layer_backward, layer_forward, loss_and_grads,
+                        net_forward, transport, transport_adjoint)
 from stag_inputs import fat_field, gaussian_full_field, gaussian_source, random_gauge_transform, random_su3_field
 
 DIMS = (4, 4, 2, 6)
@@ -94,6 +94,30 @@ def test_weight_gradients_match_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
 
 
+def test_residual_loss_gradients_match_finite_differences():
+    from oracle.dslash import apply_m
+
+    fat, lng = fat_field(DIMS, 40), random_su3_field(DIMS, 41)
+    Ft = folded_fat(fat, DIMS)
+    A = lambda v: apply_m(fat, lng, v, DIMS, 0.2)
+    W = init_weights([1, 2, 1], 42, scale=1.0)
+    pairs = [(gaussian_source(DIMS, 43)[0], None)]
+    L0, grads = loss_and_grads(Ft, W, pairs, DIMS, apply_m=A)
+    rng = np.random.default_rng(44)
+    h = 1e-6
+    for _ in range(6):
+        l = rng.integers(len(W))
+        idx = tuple(rng.integers(s) for s in W[l].shape)
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[l][idx] += h * unit
+            Wm[l][idx] -= h * unit
+            fd = (loss_and_grads(Ft, Wp, pairs, DIMS, A)[0] - loss_and_grads(Ft, Wm, pairs, DIMS, A)[0]) / (2 * h)
+            an = 2 * (grads[l][idx].real if part == "re" else grads[l][idx].imag)
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
+
+
 def _system(dims, seed, m=0.1):
     fat, lng = fat_field(dims, seed), random_su3_field(dims, seed + 1)
     return fat, lng, (lambda v: apply_m(fat, lng, v, dims, m))
@@ -129,3 +153,17 @@ def test_fcg_falls_back_when_preconditioner_stalls():
     noise = lambda r: 1e-8 * (rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape))
     res = fcg(A, noise, b, tol=1e-10, stall_window=5)
     assert res.fell_back and res.converged and res.true_resid <= 1e-10
+
+
+def test_tied_network_is_hermitian_positive():
+    """N = K^dag K built from the adjoint layers is Hermitian and positive semi-definite."""
+    fat = fat_field(DIMS, 50)
+    Ft = folded_fat(fat, DIMS)
+    W = hermitian_weights(init_weights([1, 3, 3], 51, scale=1.0))
+    u = gaussian_source(DIMS, 52)[0]
+    v = gaussian_source(DIMS, 53)[0]
+    a = np.vdot(u, net_forward(Ft, W, v, DIMS))
+    b = np.conj(np.vdot(v, net_forward(Ft, W, u, DIMS)))
+    assert abs(a - b) <= 1e-12 * abs(a)
+    q = np.vdot(v, net_forward(Ft, W, v, DIMS))
+    assert q.real > 0 and abs(q.imag) <= 1e-12 * q.real
