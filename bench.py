@@ -29,13 +29,18 @@ HBM_PEAK_GBPS = 8000.0
 # 16 links + link scales + input and output colour vectors; the xpay launch of the
 # solver also reads d at the output site.  f16 colour vectors are 12 B of codes + a 4 B scale.
 LINK = {"f64": 144, "f32": 72, "f16": 36}
+LINK12 = {"f64": 96, "f32": 48, "f16": 24}   # three-hop link stored as two rows (12 real parameters)
 LSCALE = {"f64": 0, "f32": 0, "f16": 8}
 VEC = {"f64": 48, "f32": 24, "f16": 16}
 FLOPS_PER_SITE = 1146
 
 
-def dslash_bytes_per_site(prec: str, xpay: bool = False) -> int:
-    return 16 * LINK[prec] + LSCALE[prec] + 2 * VEC[prec] + (VEC[prec] if xpay else 0)
+def link_bytes_per_site(prec: str, long12: bool) -> int:
+    return 8 * LINK[prec] + 8 * (LINK12[prec] if long12 else LINK[prec]) + LSCALE[prec]
+
+
+def dslash_bytes_per_site(prec: str, xpay: bool = False, long12: bool = True) -> int:
+    return link_bytes_per_site(prec, long12) + 2 * VEC[prec] + (VEC[prec] if xpay else 0)
 
 
 def host_info():
@@ -116,7 +121,7 @@ def run_learned_preconditioner(a, out_json):
     b_eval = torch.from_numpy(workload_sources(4)).cuda()
     lat = Lattice(dims)
     lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0,
-                   precs=("f64", "f32", a.prec))
+                   precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
     del fat, lng
     half = lat.half
     chunk = 8
@@ -185,6 +190,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap the inner iterations (for counter-collection runs; the solve then stops early)")
+    ap.add_argument("--no-long-su3", action="store_true",
+                    help="store the three-hop links with all 18 reals instead of two rows (12 parameters)")
     ap.add_argument("--train-pairs", type=int, default=0, help="workload 4: training pairs (0: the workload's 2000)")
     ap.add_argument("--epochs", type=int, default=5, help="workload 4: training epochs")
     ap.add_argument("--lr", type=float, default=2e-3, help="workload 4: Adam step size")
@@ -230,7 +237,7 @@ def main(argv=None):
     def step(prec, profile=True):
         """load_links on every lattice, then one batched solve per mass; returns the infos."""
         for p in probs:
-            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs)
+            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=not a.no_long_su3)
         infos = []
         for m in masses:
             batch = [(p["lat"], p["b"], [m] * p["nrhs"], None) for p in probs]
@@ -248,7 +255,7 @@ def main(argv=None):
         per_launch = 0.0
         for p in probs:
             groups = p["nrhs"] // r
-            site = 16 * LINK[prec] + LSCALE[prec] + r * (2 * VEC[prec]) + r * VEC[prec] / 2.0
+            site = link_bytes_per_site(prec, not a.no_long_su3) + r * (2 * VEC[prec]) + r * VEC[prec] / 2.0
             per_launch += p["lat"].half * groups * site
         avg = ms / max(calls, 1)
         sites = sum(p["lat"].half * p["nrhs"] for p in probs)
@@ -283,7 +290,8 @@ def main(argv=None):
                                f"true residual {tol}", "lattices": [list(p["dims"]) for p in probs],
                    "nrhs": [p["nrhs"] for p in probs], "masses": masses, "tol": tol,
                    "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every {rel_int} "
-                             f"iterations or after a 10x residual drop", "step": "load_links + solve"},
+                             f"iterations or after a 10x residual drop", "step": "load_links + solve",
+                   "long_links": "18 reals" if a.no_long_su3 else "12 reals (two rows, third rebuilt)"},
         "mp_iters": [max(x["iters"] for x in inf) for inf in last],
         "mp_reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
         "mp_true_resid": max(x["true_resid"] for inf in last for x in inf),

@@ -60,6 +60,10 @@ typedef enum {
 
 typedef enum { STAG_F64 = 0, STAG_F32 = 1, STAG_F16 = 2 } stag_prec;
 #define STAG_PREC_BIT(p) (1u << (p))
+/* stag_load_links flag: the three-hop links are SU(3) matrices; store two rows each (12 real
+ * parameters) and rebuild the third as (a x b)^* (Sec. 3.3, Eq. SU3rec), which moves 16% fewer bytes
+ * per Dslash.  Only correct for special unitary long links. */
+#define STAG_LONG_SU3 (1u << 8)
 
 typedef enum { STAG_PRECOND_NONE = 0, STAG_PRECOND_NET = 1 } stag_precond;
 
@@ -136,8 +140,8 @@ stag_status stag_lattice_info(stag_lattice_t lat, int32_t dims[4], int64_t* half
  * fat, lng: device complex128 link fields (layout above); lng = NULL drops the
  * three-hop term, leaving the paper's one-hop Eq. (5).  naik_coeff: c_N (-1/24
  * for the improved action).  prec_mask: STAG_PREC_BIT of every storage precision
- * to build (FP64 is always built: the true residual needs it).  Replaces any
- * previously loaded links. */
+ * to build (FP64 is always built: the true residual needs it), optionally or'ed with STAG_LONG_SU3.
+ * Replaces any previously loaded links. */
 stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng, double naik_coeff,
                             uint32_t prec_mask, void* stream);
 

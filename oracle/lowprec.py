@@ -61,6 +61,36 @@ def site_matrices(fat, lng, dims, out_parity: int, antiperiodic_t: bool = True, 
     return mats, nbr
 
 
+def folded_scalars(dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF):
+    """The real scalar folded into each of the 16 matrices of site_matrices: [V/2][16]
+    (eta_mu(n) s(start, k), times c_N for three-hop matrices and -1 for backward ones)."""
+    Lx, Ly, Lz, Lt = dims
+    par = parity(dims)
+    t, z, y, x = np.nonzero(par == out_parity)
+    n = np.stack([x, y, z, t], axis=1)
+    out = np.zeros((len(x), 16))
+    for mu in range(4):
+        e = eta_field(mu, dims)[t, z, y, x]
+        for j, (k, c) in enumerate(((1, 1.0), (3, naik))):
+            bwd = n.copy()
+            bwd[:, mu] = (n[:, mu] - k) % dims[mu]
+            for d, start, sgn in ((0, n, 1.0), (1, bwd, -1.0)):
+                s = np.ones(len(x))
+                if mu == 3 and antiperiodic_t:
+                    s = np.where(((start[:, 3] + k) // Lt) % 2 == 0, 1.0, -1.0)
+                out[:, 4 * mu + 2 * j + d] = sgn * c * e * s
+    return out
+
+
+def rebuild_third_rows(mats, scalars, ks):
+    """For matrices s U with U in SU(3), replace row 3 by (a' x b')^* / s from rows 1 and 2 (paper Sec. 3.3)."""
+    out = mats.copy()
+    for k in ks:
+        a, b = mats[:, k, 0], mats[:, k, 1]
+        out[:, k, 2] = np.conj(np.cross(a, b)) / scalars[:, k, None]
+    return out
+
+
 def apply_site_matrices(mats, nbr, chi_half):
     """out(n) = sum_k mats[n,k] chi(nbr[n,k]) in FP64."""
     return np.einsum("nkab,nkb->na", mats, chi_half[nbr])
@@ -72,22 +102,36 @@ def abs_bound_terms(mats, nbr, chi_half):
                      np.abs(chi_half[nbr].real) + np.abs(chi_half[nbr].imag))
 
 
-def round_matrices(mats, prec: str):
-    """Round the 16 matrices of each site as the storage format does."""
+K_FAT = [4 * mu + d for mu in range(4) for d in (0, 1)]
+K_LONG = [4 * mu + d for mu in range(4) for d in (2, 3)]
+
+
+def round_matrices(mats, prec: str, long12: bool = False, scalars=None):
+    """Round the 16 matrices of each site as the storage format does.
+
+    long12: the three-hop matrices are stored as their first two rows (rounded like every stored
+    value; FP16 scale over the stored entries only) and the third row is rebuilt from them with
+    the folded scalars (see folded_scalars).
+    """
     if prec == "f64":
-        return mats
-    if prec == "f32":
-        return quant.to_f32(mats)
-    if prec == "f16":
+        out = mats.copy()
+    elif prec == "f32":
+        out = quant.to_f32(mats)
+    elif prec == "f16":
         out = np.empty_like(mats)
-        # groups: one-hop k in {4mu, 4mu+1}, three-hop k in {4mu+2, 4mu+3}, over all mu
-        k_fat = [4 * mu + d for mu in range(4) for d in (0, 1)]
-        k_long = [4 * mu + d for mu in range(4) for d in (2, 3)]
-        for ks in (k_fat, k_long):
-            codes, s = quant.quantize_link_group_f16(mats[:, ks])
-            out[:, ks] = quant.dequantize_link_group_f16(codes, s)
-        return out
-    raise ValueError(prec)
+        codes, s = quant.quantize_link_group_f16(mats[:, K_FAT])
+        out[:, K_FAT] = quant.dequantize_link_group_f16(codes, s)
+        if long12:
+            codes, s = quant.quantize_link_group_f16(mats[:, K_LONG][:, :, :2, :])
+            out[:, K_LONG, :2, :] = quant.dequantize_link_group_f16(codes, s)
+        else:
+            codes, s = quant.quantize_link_group_f16(mats[:, K_LONG])
+            out[:, K_LONG] = quant.dequantize_link_group_f16(codes, s)
+    else:
+        raise ValueError(prec)
+    if long12:
+        out = rebuild_third_rows(out, scalars, K_LONG)
+    return out
 
 
 def round_spinor(v, prec: str):

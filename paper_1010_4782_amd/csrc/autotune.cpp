@@ -21,7 +21,7 @@ std::map<std::string, DslashShape> g_table;   // tuned or pinned shapes
 
 std::string key_of(const BatchHost& bh, const std::vector<const stag_lattice_s*>& lats, int prec) {
   std::ostringstream k;
-  k << "p" << prec;
+  k << "p" << prec << (bh.long12 ? "c" : "");
   for (size_t i = 0; i < lats.size(); ++i) {
     const int* d = lats[i]->dims;
     k << ":" << d[0] << "x" << d[1] << "x" << d[2] << "x" << d[3] << "/" << bh.probs[i].nrhs;

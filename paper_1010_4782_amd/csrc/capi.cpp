@@ -179,6 +179,7 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
   bh.pstride = pstride;
   bh.nslots = nrhs;
   bh.max_half = L->g.half;
+  bh.long12 = L->g.long12 != 0;
   return STAG_OK;
 }
 
@@ -243,6 +244,7 @@ stag_status stag_create_lattice(const int32_t dims[4], int32_t t_antiperiodic, s
   L->antiper = t_antiperiodic;
   L->device = dev;
   L->g = make_geo(L->dims);
+  L->g.antiper = t_antiperiodic;
   *out = L;
   return STAG_OK;
   STAG_GUARD_END
@@ -270,21 +272,25 @@ stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng
   if (!lat) return arg_error("lattice is NULL");
   if (!fat) return arg_error("fat links must not be NULL");
   if (!std::isfinite(naik_coeff)) return arg_error("naik_coeff must be finite");
-  if (prec_mask & ~0x7u) return arg_error("prec_mask has unknown bits");
+  if (prec_mask & ~(0x7u | STAG_LONG_SU3)) return arg_error("prec_mask has unknown bits");
+  const bool c12 = (prec_mask & STAG_LONG_SU3) != 0;
+  if (c12 && (!lng || naik_coeff == 0.0)) return arg_error("STAG_LONG_SU3 needs long links and a nonzero naik_coeff");
   int dev = -1;
   STAG_HIP_TRY(hipGetDevice(&dev));
   if (dev != lat->device) return arg_error("the current HIP device is not the lattice's device");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  prec_mask |= STAG_PREC_BIT(STAG_F64);
+  prec_mask = (prec_mask & 0x7u) | STAG_PREC_BIT(STAG_F64);
   const size_t padded = (size_t)ceil_div(lat->g.half, kWave) * kWave;
   lat->loaded = false;
+  lat->g.long12 = c12 ? 1 : 0;
+  lat->g.cn_inv = c12 ? 1.0 / naik_coeff : 0.0;
   for (int p = 0; p < 3; ++p) {
     if (!(prec_mask & STAG_PREC_BIT(p))) {
       for (auto& b : lat->links[p]) b.release();
       continue;
     }
     for (int par = 0; par < 2; ++par) {
-      STAG_HIP_TRY(lat->links[p][par].ensure(padded * kLinks * link_bytes(p)));
+      STAG_HIP_TRY(lat->links[p][par].ensure(padded / kWave * link_block_bytes(p, c12)));
       float* ls = nullptr;
       if (p == P16) {
         STAG_HIP_TRY(lat->lscale[par].ensure(padded * 2 * sizeof(float)));
@@ -428,6 +434,7 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   if (wg != 0 && nrhs % rhs_per_lane) return arg_error("rhs_per_lane must divide nrhs");
   BatchHost bh;
   bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0});
+  bh.long12 = lat->g.long12 != 0;
   pin_shape(single_key(bh, lat, prec), DslashShape{wg, rhs_per_lane});
   return STAG_OK;
   STAG_GUARD_END

@@ -49,28 +49,42 @@ __device__ __forceinline__ unsigned pack_h2(float a, float b) {
   return __builtin_bit_cast(unsigned, h);
 }
 
+// ---- global-memory pointers -----------------------------------------------------
+// Buffers reach the kernels through structs in device memory, so the compiler cannot tell their
+// address space and emits flat loads, which count against both vmcnt and lgkmcnt and force coarse
+// waits.  Every buffer here is in global memory: casting to address space 1 gives global loads.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> using gptr_w = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const void* p) { return (gptr<T>)p; }
+template <typename T> __device__ __forceinline__ gptr_w<T> as_global_w(void* p) { return (gptr_w<T>)p; }
+
 // ---- colour vectors ---------------------------------------------------------
 // f64: 3 x double2 (48 B); f32: 3 x float2 (24 B); f16: uint4 = 6 binary16 codes + binary32 scale (16 B).
 template <int P> __device__ __forceinline__ void load_spinor(const void* base, long s, Cx<typename RealOf<P>::T> v[3]);
 
 template <> __device__ __forceinline__ void load_spinor<P64>(const void* base, long s, Cx<double> v[3]) {
-  const double2* p = reinterpret_cast<const double2*>(base) + 3 * s;
+  gptr<d2v> p = as_global<d2v>(base) + 3 * s;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double2 w = p[c];
+    d2v w = p[c];
     v[c] = Cx<double>{w.x, w.y};
   }
 }
 template <> __device__ __forceinline__ void load_spinor<P32>(const void* base, long s, Cx<float> v[3]) {
-  const float2* p = reinterpret_cast<const float2*>(base) + 3 * s;
+  gptr<f2v> p = as_global<f2v>(base) + 3 * s;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    float2 w = p[c];
+    f2v w = p[c];
     v[c] = Cx<float>{w.x, w.y};
   }
 }
 template <> __device__ __forceinline__ void load_spinor<P16>(const void* base, long s, Cx<float> v[3]) {
-  const uint4 w = reinterpret_cast<const uint4*>(base)[s];
+  const u4v w = as_global<u4v>(base)[s];
   const float sc = __uint_as_float(w.w);
   v[0] = unpack_h2(w.x, sc);
   v[1] = unpack_h2(w.y, sc);
@@ -81,14 +95,14 @@ template <> __device__ __forceinline__ void load_spinor<P16>(const void* base, l
 template <int P> __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]);
 
 template <> __device__ __forceinline__ void store_spinor<P64>(void* base, long s, Cx<double> v[3]) {
-  double2* p = reinterpret_cast<double2*>(base) + 3 * s;
+  gptr_w<d2v> p = as_global_w<d2v>(base) + 3 * s;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = make_double2(v[c].re, v[c].im);
+  for (int c = 0; c < 3; ++c) p[c] = d2v{v[c].re, v[c].im};
 }
 template <> __device__ __forceinline__ void store_spinor<P32>(void* base, long s, Cx<float> v[3]) {
-  float2* p = reinterpret_cast<float2*>(base) + 3 * s;
+  gptr_w<f2v> p = as_global_w<f2v>(base) + 3 * s;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = make_float2(v[c].re, v[c].im);
+  for (int c = 0; c < 3; ++c) p[c] = f2v{v[c].re, v[c].im};
 }
 template <> __device__ __forceinline__ void store_spinor<P16>(void* base, long s, Cx<float> v[3]) {
   float m = 0.f;
@@ -103,52 +117,58 @@ template <> __device__ __forceinline__ void store_spinor<P16>(void* base, long s
     w.x = w.y = w.z = 0u;
   }
   w.w = __float_as_uint(m);
-  reinterpret_cast<uint4*>(base)[s] = w;
+  as_global_w<u4v>(base)[s] = u4v{w.x, w.y, w.z, w.w};
   v[0] = unpack_h2(w.x, m);
   v[1] = unpack_h2(w.y, m);
   v[2] = unpack_h2(w.z, m);
 }
 
 // ---- packed links -----------------------------------------------------------
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef unsigned u4v __attribute__((ext_vector_type(4)));
+// A slot holds, for the 64 lanes of a block, each lane's link as 16-byte chunks: chunk j of all 64
+// lanes is contiguous (one wave load = 1 KiB), and a narrower tail chunk follows the full ones.
+// rows = 3 loads the whole matrix, rows = 2 the first two rows of a compressed three-hop link.
 
-// Links for one output parity are stored per block of 64 output sites and per
-// link k as 16-byte chunks: chunk j of (block, k) holds, for the 64 lanes in
-// order, the j-th 16-byte piece of each lane's 9 complex numbers.  A wave's
-// load of one chunk is therefore one contiguous 1 KiB (the tail chunk is
-// narrower).  Byte offset of (block, k): (block * 16 + k) * 64 * link_bytes(P).
-template <int P> __device__ __forceinline__ void load_link(const char* base, long blk, int k, int lane,
-                                                           float scale, Cx<typename RealOf<P>::T> u[9]);
+template <int P, int ROWS>
+__device__ __forceinline__ void load_link_rows(const char* slot, int lane, float scale, Cx<typename RealOf<P>::T> u[9]);
 
-template <> __device__ __forceinline__ void load_link<P64>(const char* base, long blk, int k, int lane, float,
-                                                           Cx<double> u[9]) {
-  const d2v* p = reinterpret_cast<const d2v*>(base + (blk * kLinks + k) * (long)(kWave * 144)) + lane;
+template <> __device__ __forceinline__ void load_link_rows<P64, 3>(const char* slot, int lane, float, Cx<double> u[9]) {
+  gptr<d2v> p = as_global<d2v>(slot) + lane;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
     d2v w = __builtin_nontemporal_load(p + e * kWave);
     u[e] = Cx<double>{w.x, w.y};
   }
 }
-template <> __device__ __forceinline__ void load_link<P32>(const char* base, long blk, int k, int lane, float,
-                                                           Cx<float> u[9]) {
-  const char* b = base + (blk * kLinks + k) * (long)(kWave * 72);
-  const f4v* p = reinterpret_cast<const f4v*>(b) + lane;
+template <> __device__ __forceinline__ void load_link_rows<P64, 2>(const char* slot, int lane, float, Cx<double> u[9]) {
+  gptr<d2v> p = as_global<d2v>(slot) + lane;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    d2v w = __builtin_nontemporal_load(p + e * kWave);
+    u[e] = Cx<double>{w.x, w.y};
+  }
+}
+template <> __device__ __forceinline__ void load_link_rows<P32, 3>(const char* slot, int lane, float, Cx<float> u[9]) {
+  gptr<f4v> p = as_global<f4v>(slot) + lane;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     f4v w = __builtin_nontemporal_load(p + j * kWave);
     u[2 * j] = Cx<float>{w.x, w.y};
     u[2 * j + 1] = Cx<float>{w.z, w.w};
   }
-  f2v w = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(b + 4 * kWave * 16) + lane);
+  f2v w = __builtin_nontemporal_load(as_global<f2v>(slot + 4 * kWave * 16) + lane);
   u[8] = Cx<float>{w.x, w.y};
 }
-template <> __device__ __forceinline__ void load_link<P16>(const char* base, long blk, int k, int lane, float s,
-                                                           Cx<float> u[9]) {
-  const char* b = base + (blk * kLinks + k) * (long)(kWave * 36);
-  const u4v* p = reinterpret_cast<const u4v*>(b) + lane;
+template <> __device__ __forceinline__ void load_link_rows<P32, 2>(const char* slot, int lane, float, Cx<float> u[9]) {
+  gptr<f4v> p = as_global<f4v>(slot) + lane;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    f4v w = __builtin_nontemporal_load(p + j * kWave);
+    u[2 * j] = Cx<float>{w.x, w.y};
+    u[2 * j + 1] = Cx<float>{w.z, w.w};
+  }
+}
+template <> __device__ __forceinline__ void load_link_rows<P16, 3>(const char* slot, int lane, float s, Cx<float> u[9]) {
+  gptr<u4v> p = as_global<u4v>(slot) + lane;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     u4v w = __builtin_nontemporal_load(p + j * kWave);
@@ -157,8 +177,47 @@ template <> __device__ __forceinline__ void load_link<P16>(const char* base, lon
     u[4 * j + 2] = unpack_h2(w.z, s);
     u[4 * j + 3] = unpack_h2(w.w, s);
   }
-  unsigned w = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(b + 2 * kWave * 16) + lane);
+  unsigned w = __builtin_nontemporal_load(as_global<unsigned>(slot + 2 * kWave * 16) + lane);
   u[8] = unpack_h2(w, s);
+}
+template <> __device__ __forceinline__ void load_link_rows<P16, 2>(const char* slot, int lane, float s, Cx<float> u[9]) {
+  u4v w = __builtin_nontemporal_load(as_global<u4v>(slot) + lane);
+  u[0] = unpack_h2(w.x, s);
+  u[1] = unpack_h2(w.y, s);
+  u[2] = unpack_h2(w.z, s);
+  u[3] = unpack_h2(w.w, s);
+  u2v t = __builtin_nontemporal_load(as_global<u2v>(slot + kWave * 16) + lane);
+  u[4] = unpack_h2(t.x, s);
+  u[5] = unpack_h2(t.y, s);
+}
+
+// Third row of s U for U in SU(3) from its first two rows a' = s a, b' = s b (paper Sec. 3.3,
+// c = (a x b)^*):  s c = (a' x b')^* / s.
+template <typename T>
+__device__ __forceinline__ void rebuild_row3(Cx<T> u[9], T inv_s) {
+  const Cx<T>* a = u;
+  const Cx<T>* b = u + 3;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+    // (a x b)_i = a_i1 b_i2 - a_i2 b_i1
+    const T re = a[i1].re * b[i2].re - a[i1].im * b[i2].im - (a[i2].re * b[i1].re - a[i2].im * b[i1].im);
+    const T im = a[i1].re * b[i2].im + a[i1].im * b[i2].re - (a[i2].re * b[i1].im + a[i2].im * b[i1].re);
+    u[6 + i] = Cx<T>{re * inv_s, -im * inv_s};
+  }
+}
+
+// Load the packed matrix k of the output site in block blk (lane = site % 64); C12: the three-hop
+// matrices are stored as two rows (the caller rebuilds the third).  The layout is a compile-time
+// choice so that the unrolled link loop stays straight-line code.
+template <int P, bool C12>
+__device__ __forceinline__ void load_link(const char* base, long blk, int k, int lane, float scale,
+                                          Cx<typename RealOf<P>::T> u[9]) {
+  const char* slot = base + link_slot_offset(P, C12, blk, k);
+  if (C12 && (k & 3) >= 2)
+    load_link_rows<P, 2>(slot, lane, scale, u);
+  else
+    load_link_rows<P, 3>(slot, lane, scale, u);
 }
 
 // ---- geometry -----------------------------------------------------------------
@@ -191,6 +250,21 @@ __device__ __forceinline__ int neighbour(const Site& s, const Geo& g, int mu, in
   int c = mu == 1 ? s.y : (mu == 2 ? s.z : s.t);
   int cn = fwd ? wrap_fwd(c, h, g.L[mu]) : wrap_bwd(c, h, g.L[mu]);
   return s.cb + (cn - c) * g.stride[mu];
+}
+
+// Sign of eta_mu(n) s(start, 3) (times -1 for the backward term): the folded scalar of the three-hop
+// matrix k = 4 mu + j (j = 2 forward, 3 backward) of output site s is c_N times this sign.
+__device__ __forceinline__ int long_sign(const Site& s, const Geo& g, int mu, bool fwd) {
+  const int eta_bits = mu == 0 ? 0 : (mu == 1 ? s.x : (mu == 2 ? s.x + s.y : s.x + s.y + s.z));
+  int neg = (eta_bits & 1) ^ (fwd ? 0 : 1);
+  if (mu == 3) {
+    // floor((start + 3) / L_t) for 0 <= start < L_t, L_t >= 2, is (start+3 >= L_t) + (start+3 >= 2 L_t):
+    // compares instead of a division or a branch keep the unrolled link loop straight-line code.
+    const int start = fwd ? s.t : wrap_bwd(s.t, g.h3[3], g.L[3]);
+    const int wraps = (start + 3 >= g.L[3]) ^ (start + 3 >= 2 * g.L[3]);
+    neg ^= wraps & g.antiper;
+  }
+  return neg ? -1 : 1;
 }
 
 // ---- reductions ---------------------------------------------------------------

@@ -13,7 +13,7 @@
 
 namespace stag {
 
-template <int P, int R, int EPI>
+template <int P, int R, int EPI, bool C12>
 __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
                                                    int b_id, int gate) {
   using T = typename RealOf<P>::T;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
   const char* lbase = reinterpret_cast<const char*>(pd->links[P][out_par]);
   float sc_fat = 1.f, sc_long = 1.f;
   if (P == P16) {
-    const float* ls = pd->lscale[out_par] + blk * 2 * kWave + lane;
+    gptr<float> ls = as_global<float>(pd->lscale[out_par]) + blk * 2 * kWave + lane;
     sc_fat = ls[0];
     sc_long = ls[kWave];
   }
@@ -67,7 +67,8 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
       const int hop = j < 2 ? g.h1[mu] : g.h3[mu];
       const int nb = neighbour(s, g, mu, hop, (j & 1) == 0);
       Cx<T> u[9];
-      load_link<P>(lbase, blk, 4 * mu + j, lane, j < 2 ? sc_fat : sc_long, u);
+      load_link<P, C12>(lbase, blk, 4 * mu + j, lane, j < 2 ? sc_fat : sc_long, u);
+      if (C12 && j >= 2) rebuild_row3(u, (T)(long_sign(s, g, mu, j == 2) * g.cn_inv));
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!on[r]) continue;
@@ -143,23 +144,23 @@ Batch make_batch(const BatchHost& bh, int wg, int r) {
   return B;
 }
 
-template <int P, int R>
+template <int P, int R, bool C12>
 static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                            int gate, int wg, hipStream_t st) {
   switch (epi) {
     case EPI_PLAIN:
-      k_dslash<P, R, EPI_PLAIN><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_PLAIN, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_XPAY_DOT:
-      k_dslash<P, R, EPI_XPAY_DOT><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_XPAY_DOT, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_RESID:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_RESID><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_RESID, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_XPAY:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_XPAY><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_XPAY, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     default:
       return hipErrorInvalidValue;
@@ -167,14 +168,14 @@ static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int i
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, bool C12>
 static hipError_t dslash_p(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                            int gate, int wg, int r, hipStream_t st) {
   switch (r) {
-    case 1: return dslash_r<P, 1>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 2: return dslash_r<P, 2>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 4: return dslash_r<P, 4>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 8: return dslash_r<P, 8>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 1: return dslash_r<P, 1, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 2: return dslash_r<P, 2, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 4: return dslash_r<P, 4, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 8: return dslash_r<P, 8, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -185,11 +186,19 @@ hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, in
   const Batch B = make_batch(bh, wg, r);
   const int nblk = B.block_start[B.nprob];
   if (nblk == 0) return hipSuccess;
+  const bool c12 = bh.long12;
   switch (prec) {
-    case P64: return dslash_p<P64>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    case P32: return dslash_p<P32>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    case P16: return dslash_p<P16>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    default: return hipErrorInvalidValue;
+    case P64:
+      return c12 ? dslash_p<P64, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
+                 : dslash_p<P64, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    case P32:
+      return c12 ? dslash_p<P32, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
+                 : dslash_p<P32, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    case P16:
+      return c12 ? dslash_p<P16, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
+                 : dslash_p<P16, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
+    default:
+      return hipErrorInvalidValue;
   }
 }
 

@@ -29,6 +29,7 @@ struct BatchHost {
   int pstride = 0;
   int nslots = 0;
   int max_half = 0;
+  bool long12 = false;   // every lattice of the batch stores its three-hop links as two rows
 };
 
 // Block map for a launch with `wg` sites per workgroup and `r` right-hand sides per lane.

@@ -30,7 +30,10 @@ __device__ __forceinline__ void transported(const NetLayerArgs& a, const Site& s
   const bool fwd = d <= 4;
   const int nb = neighbour(s, a.g, mu, a.g.h1[mu], fwd);
   Cx<float> u[9];
-  load_link<P32>(a.links, blk, 4 * mu + (fwd ? 0 : 1), lane, 1.f, u);
+  if (a.g.long12)
+    load_link<P32, true>(a.links, blk, 4 * mu + (fwd ? 0 : 1), lane, 1.f, u);
+  else
+    load_link<P32, false>(a.links, blk, 4 * mu + (fwd ? 0 : 1), lane, 1.f, u);
   if (!fwd)
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = Cx<float>{-u[e].re, -u[e].im};

@@ -80,14 +80,15 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
   const long blk = cb_raw >> 6;
   const int lane = cb_raw & 63;
   float scale[2] = {0.f, 0.f};
+  const bool c12 = g.long12 != 0;
   if (P == P16) {
     for (int k = 0; k < kLinks && live; ++k) {
       double2 u[9];
       folded_link(fat, lng, naik, g, antiper, s, k, u);
       const int grp = (k >> 1) & 1;
+      const int nst = (c12 && grp) ? 6 : 9;  // stored entries (two rows of a compressed three-hop link)
       double m = 0.0;
-#pragma unroll
-      for (int e = 0; e < 9; ++e) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
+      for (int e = 0; e < nst; ++e) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
       scale[grp] = fmaxf(scale[grp], (float)m);  // float rounding of a max equals the max of the roundings
     }
     lscale[blk * 2 * kWave + lane] = scale[0];
@@ -101,17 +102,16 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
 #pragma unroll
       for (int e = 0; e < 9; ++e) u[e] = make_double2(0.0, 0.0);
     }
-    char* base = out + (blk * kLinks + k) * (long)(kWave * link_bytes(P));
+    char* base = out + link_slot_offset(P, c12, blk, k);
+    const bool two_rows = c12 && ((k & 3) >= 2);
     if (P == P64) {
       double2* o = reinterpret_cast<double2*>(base) + lane;
-#pragma unroll
-      for (int e = 0; e < 9; ++e) o[e * kWave] = u[e];
+      for (int e = 0; e < (two_rows ? 6 : 9); ++e) o[e * kWave] = u[e];
     } else if (P == P32) {
       float4* o = reinterpret_cast<float4*>(base) + lane;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < (two_rows ? 3 : 4); ++j)
         o[j * kWave] = make_float4((float)u[2 * j].x, (float)u[2 * j].y, (float)u[2 * j + 1].x, (float)u[2 * j + 1].y);
-      reinterpret_cast<float2*>(base + 4 * kWave * 16)[lane] = make_float2((float)u[8].x, (float)u[8].y);
+      if (!two_rows) reinterpret_cast<float2*>(base + 4 * kWave * 16)[lane] = make_float2((float)u[8].x, (float)u[8].y);
     } else {
       const float sc = scale[(k >> 1) & 1];
       h2v h[9];
@@ -121,11 +121,18 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
         h[e].y = f16_code(u[e].y, sc);
       }
       uint4* o = reinterpret_cast<uint4*>(base) + lane;
+      if (two_rows) {
+        o[0] = make_uint4(__builtin_bit_cast(unsigned, h[0]), __builtin_bit_cast(unsigned, h[1]),
+                          __builtin_bit_cast(unsigned, h[2]), __builtin_bit_cast(unsigned, h[3]));
+        reinterpret_cast<uint2*>(base + kWave * 16)[lane] =
+            make_uint2(__builtin_bit_cast(unsigned, h[4]), __builtin_bit_cast(unsigned, h[5]));
+      } else {
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        o[j * kWave] = make_uint4(__builtin_bit_cast(unsigned, h[4 * j]), __builtin_bit_cast(unsigned, h[4 * j + 1]),
-                                  __builtin_bit_cast(unsigned, h[4 * j + 2]), __builtin_bit_cast(unsigned, h[4 * j + 3]));
-      reinterpret_cast<unsigned*>(base + 2 * kWave * 16)[lane] = __builtin_bit_cast(unsigned, h[8]);
+        for (int j = 0; j < 2; ++j)
+          o[j * kWave] = make_uint4(__builtin_bit_cast(unsigned, h[4 * j]), __builtin_bit_cast(unsigned, h[4 * j + 1]),
+                                    __builtin_bit_cast(unsigned, h[4 * j + 2]), __builtin_bit_cast(unsigned, h[4 * j + 3]));
+        reinterpret_cast<unsigned*>(base + 2 * kWave * 16)[lane] = __builtin_bit_cast(unsigned, h[8]);
+      }
     }
   }
 }

@@ -251,6 +251,8 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     if (!(q.lat->built & STAG_PREC_BIT(prm.prec))) return fail_arg("the requested precision was not packed by load_links");
     if (q.lat->device != dev) return fail_arg("lattice belongs to another device than the current one");
     if (!seen.insert(q.lat).second) return fail_arg("a lattice may appear only once per batch (merge its right-hand sides)");
+    if (q.lat->g.long12 != probs[0].lat->g.long12)
+      return fail_arg("the lattices of a batch must all use the same long-link storage (STAG_LONG_SU3 or not)");
     for (int r = 0; r < q.nrhs; ++r)
       if (!std::isfinite(q.mass[r])) return fail_arg("mass must be finite");
     nslots += q.nrhs;
@@ -296,6 +298,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
   }
   R.bh.nslots = nslots;
   R.bh.max_half = max_half;
+  R.bh.long12 = probs[0].lat->g.long12 != 0;
   R.bh.pstride = ceil_div(max_half, kWave);
   STAG_HIP_TRY(ctl.probs.ensure(sizeof(ProbDev) * kMaxProb));
   STAG_HIP_TRY(ctl.scal.ensure(sizeof(Scal) * nslots));

@@ -14,14 +14,32 @@ constexpr int kPartialSlots = 3; // reduction partials per slot kept apart (up t
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
 
-// Storage of one packed link per lane: 9 complex numbers.
+// Storage of one packed link per lane: 9 complex numbers, or 6 (two rows) for a three-hop link stored
+// with 12 real parameters (its third row is rebuilt from the first two; SU(3) links only).
 __host__ __device__ constexpr int link_bytes(int p) { return p == P64 ? 144 : (p == P32 ? 72 : 36); }
+__host__ __device__ constexpr int link12_bytes(int p) { return p == P64 ? 96 : (p == P32 ? 48 : 24); }
+
+// Packed links of one output parity, per block of 64 output sites: eight one-hop slots (k = 4 mu + j,
+// j = 0 forward, 1 backward -> slot 2 mu + j) of link_bytes(P) per lane, then eight three-hop slots
+// (j = 2, 3 -> slot 2 mu + j - 2) of link_bytes(P) or, compressed, link12_bytes(P) per lane.
+__host__ __device__ constexpr long link_block_bytes(int p, bool c12) {
+  return 64L * 8 * (link_bytes(p) + (c12 ? link12_bytes(p) : link_bytes(p)));
+}
+__host__ __device__ inline long link_slot_offset(int p, bool c12, long blk, int k) {
+  const int mu = k >> 2, j = k & 3;
+  const long b = blk * link_block_bytes(p, c12);
+  if (j < 2) return b + (long)(2 * mu + j) * 64 * link_bytes(p);
+  return b + 64L * 8 * link_bytes(p) + (long)(2 * mu + j - 2) * 64 * (c12 ? link12_bytes(p) : link_bytes(p));
+}
 // Storage of one colour vector (3 complex) per site.  f16: six binary16 codes + one binary32 scale.
 __host__ __device__ constexpr int spinor_bytes(int p) { return p == P64 ? 48 : (p == P32 ? 24 : 16); }
 
 // Lattice geometry in the even-odd index cb = lex >> 1.
 struct Geo {
   int L[4];        // Lx, Ly, Lz, Lt
+  int antiper;     // 1: antiperiodic time direction
+  int long12;      // 1: three-hop links stored with 12 real parameters
+  double cn_inv;   // 1 / c_N (rebuilding the third row of a compressed three-hop link)
   int Xh;          // Lx / 2
   int half;        // V / 2
   int stride[4];   // cb distance of one step in y, z, t (stride[0] unused: x is handled by parity)

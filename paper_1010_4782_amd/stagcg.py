@@ -103,7 +103,8 @@ class Lattice:
         return nrhs
 
     def load_links(self, fat: torch.Tensor, lng: torch.Tensor | None = None, naik: float = -1.0 / 24.0,
-                   precs: Iterable[str] = ("f64",), stream=None):
+                   precs: Iterable[str] = ("f64",), long_su3: bool = False, stream=None):
+        """Pack the links; long_su3=True stores the (SU(3)) three-hop links with 12 real parameters."""
         Lx, Ly, Lz, Lt = self.dims
         shape = (4, Lt, Lz, Ly, Lx, 3, 3)
         _dev_tensor(fat, "fat")
@@ -113,7 +114,7 @@ class Lattice:
             _dev_tensor(lng, "lng")
             if tuple(lng.shape) != shape:
                 raise ValueError(f"long links must have shape {shape}")
-        mask = 0
+        mask = 0x100 if long_su3 else 0
         for p in precs:
             mask |= 1 << PREC[p]
         check(lib().stag_load_links(self._h, fat.data_ptr(), None if lng is None else lng.data_ptr(), float(naik),

@@ -278,3 +278,60 @@ def test_batched_solve_with_autotune(gpu_lib):
             assert infos[k]["converged"] == 1
             assert true_residual(lambda v: apply_m(fat, lng, v, dims, 0.05), b[r], x[r]) <= 1.05e-10
             k += 1
+
+
+def make12(dims, seed, precs):
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    fat = fat_field(dims, seed)
+    lng = random_su3_field(dims, seed + 1)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=precs, long_su3=True)
+    return lat, fat, lng
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (2, 4, 6, 8), (4, 2, 8, 2)])
+def test_dslash_f64_twelve_parameter_long_links(gpu_lib, dims):
+    """Long links stored as two rows (Sec. 3.3): FP64 Dslash still matches the exact operator to 1e-12."""
+    print(f"dslash f64 long12 {dims}", flush=True)
+    lat, fat, lng = make12(dims, 101, ("f64",))
+    b = gaussian_source(dims, 102, 2)
+    for par in (0, 1):
+        out = lat.dslash(torch.from_numpy(b).cuda(), par).cpu().numpy()
+        for r in range(2):
+            assert rel(out[r], dslash_eo(fat, lng, b[r], dims, par)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_dslash_lowprec_twelve_parameter_within_bound(gpu_lib, prec):
+    dims = (6, 4, 4, 6)
+    print(f"dslash {prec} long12", flush=True)
+    lat, fat, lng = make12(dims, 103, ("f64", prec))
+    b = gaussian_source(dims, 104)[0]
+    u32 = 2.0 ** -24
+    for par in (0, 1):
+        out = lat.dslash(torch.from_numpy(b).cuda(), par, prec=prec).cpu().numpy()
+        mats, nbr = lowprec.site_matrices(fat, lng, dims, par)
+        sc = lowprec.folded_scalars(dims, par)
+        mats_q = lowprec.round_matrices(mats, prec, long12=True, scalars=sc)
+        b_q = lowprec.round_spinor(b, prec)
+        ref = lowprec.apply_site_matrices(mats_q, nbr, b_q)
+        # rebuilding the third row in binary32 adds a few more roundings per three-hop term
+        bound = 300 * u32 * lowprec.abs_bound_terms(mats_q, nbr, b_q)
+        if prec == "f16":
+            s = np.max(np.abs(np.stack([ref.real, ref.imag], -1)).reshape(len(ref), -1), axis=1)
+            bound = bound + (2.0 ** -11) * s[:, None] * 1.001
+        assert np.all(np.abs(out.real - ref.real) <= bound), (par, float((np.abs(out.real - ref.real) / bound).max()))
+        assert np.all(np.abs(out.imag - ref.imag) <= bound), par
+
+
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+def test_cg_with_twelve_parameter_long_links(gpu_lib, prec):
+    dims = (8, 8, 8, 8)
+    print(f"cg long12 {prec}", flush=True)
+    lat, fat, lng = make12(dims, 105, ("f64", "f16"))
+    m = 0.05
+    b = gaussian_source(dims, 106)
+    x, info = lat.cg_solve(torch.from_numpy(b).cuda(), m, prec=prec)
+    assert info[0]["converged"] == 1
+    assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[0], x.cpu().numpy()[0]) <= 1.05e-10

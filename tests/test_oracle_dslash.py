@@ -196,3 +196,28 @@ def test_site_matrices_reproduce_operator(dims):
     for par in (0, 1):
         mats, nbr = site_matrices(fat, lng, dims, par)
         np.testing.assert_allclose(apply_site_matrices(mats, nbr, v), dslash_eo(fat, lng, v, dims, par), atol=1e-13)
+
+
+def test_su3_third_row_is_conjugate_cross_product():
+    """Paper Sec. 3.3, Eq. SU3rec: for U in SU(3), row 3 = (row 1 x row 2)^*."""
+    U = random_su3_field((4, 4, 4, 4), 91).reshape(-1, 3, 3)
+    np.testing.assert_allclose(U[:, 2], np.conj(np.cross(U[:, 0], U[:, 1])), atol=1e-14)
+    assert np.abs(np.linalg.det(U) - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 6, 8), (2, 4, 2, 2), (4, 2, 4, 6)])
+def test_twelve_parameter_long_links_rebuild_the_operator(dims):
+    """Rebuilding the three-hop matrices from two rows and the folded scalars leaves D unchanged."""
+    from oracle.lowprec import K_LONG, apply_site_matrices, folded_scalars, rebuild_third_rows, site_matrices
+
+    fat, lng = links(dims, 92)
+    v = gaussian_source(dims, 93)[0]
+    for par in (0, 1):
+        mats, nbr = site_matrices(fat, lng, dims, par)
+        sc = folded_scalars(dims, par)
+        # the scalars are what the matrices carry: mats = s * (an SU(3) matrix) for three-hop k
+        for k in K_LONG:
+            np.testing.assert_allclose(np.abs(np.linalg.det(mats[:, k])), np.abs(sc[:, k]) ** 3, rtol=1e-12)
+        reb = rebuild_third_rows(mats, sc, K_LONG)
+        np.testing.assert_allclose(reb, mats, atol=1e-15)
+        np.testing.assert_allclose(apply_site_matrices(reb, nbr, v), dslash_eo(fat, lng, v, dims, par), atol=1e-13)
