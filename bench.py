@@ -190,6 +190,9 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap the inner iterations (for counter-collection runs; the solve then stops early)")
+    ap.add_argument("--profile-every", type=int, default=10,
+                    help="bracket the Dslash launches of every k-th CG iteration with HIP events (each event "
+                         "record idles the GPU for a few us, so timing every iteration would slow the solve)")
     ap.add_argument("--no-long-su3", action="store_true",
                     help="store the three-hop links with all 18 reals instead of two rows (12 parameters)")
     ap.add_argument("--train-pairs", type=int, default=0, help="workload 4: training pairs (0: the workload's 2000)")
@@ -234,8 +237,9 @@ def main(argv=None):
     masses = w["masses"]
     precs = ("f64", a.prec)
 
-    def step(prec, profile=True):
+    def step(prec, profile=None):
         """load_links on every lattice, then one batched solve per mass; returns the infos."""
+        profile = a.profile_every if profile is None else profile
         for p in probs:
             p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=not a.no_long_su3)
         infos = []

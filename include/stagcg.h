@@ -83,7 +83,9 @@ typedef struct {
   stag_net_t net;            /* network for STAG_PRECOND_NET (built on the solve's lattice) */
   int32_t stall_window;      /* FCG: fall back to plain CG if ||r_k|| > stall_ratio ||r_{k-w}|| (default 10) */
   double stall_ratio;        /* default 0.9 */
-  int32_t profile;           /* 1: time every Dslash launch with HIP events (stag_cg_info.dslash_ms) */
+  int32_t profile;           /* k > 0: time the Dslash launches of every k-th inner iteration with HIP events
+                                (stag_cg_info.dslash_ms); each timed iteration idles the GPU for a few us
+                                per event, so k of 10 or more keeps the solve time representative */
   int32_t history_len;       /* record the first history_len (alpha, beta) pairs per RHS into history */
   double* history;           /* host [nrhs][history_len][2] or NULL */
   int32_t autotune;          /* 1: time the Dslash launch shapes on first use of a (lattices, nrhs, prec) key */
@@ -100,11 +102,12 @@ typedef struct {
   int32_t status;            /* stag_status of this right-hand side */
   double true_resid;         /* ||b - M x|| / ||b|| of the returned x, computed in FP64 on the GPU */
   double ms;                 /* wall time of the whole call (same for every RHS of a call) */
-  double dslash_ms;          /* profile=1: summed duration of the inner-iteration Dslash launches that did
-                                work (launches whose right-hand sides had all stopped are left out) */
-  int32_t dslash_calls;      /* profile=1: number of those launches */
+  double dslash_ms;          /* profile>0: summed time of the timed inner-iteration Dslash launches: the two
+                                launches of one operator application are bracketed by one event pair, and
+                                pairs whose right-hand sides had all stopped are left out */
+  int32_t dslash_calls;      /* profile>0: number of launches in that time */
   int32_t dslash_prec;       /* precision of the timed Dslash launches (inner iteration precision) */
-  double dslash_sites;       /* profile=1: output sites x RHS processed per timed launch, averaged */
+  double dslash_sites;       /* profile>0: output sites x RHS processed per timed launch, averaged */
   int32_t dslash_wg;         /* launch shape used by the inner-iteration Dslash: sites per workgroup */
   int32_t dslash_rhs;        /* ... and right-hand sides per lane */
 } stag_cg_info;

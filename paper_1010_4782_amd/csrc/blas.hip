@@ -291,10 +291,15 @@ __global__ __launch_bounds__(kMaxWG) void k_fcg_beta_dot(Batch B, int gate) {
   }
 }
 
-// One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.
-__global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
-                                                  int aux_wg, double* hist, int hist_stride) {
-  __shared__ double lds[12];
+// One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.  The
+// partials (about 2^14 per slot on the largest lattices) come from HBM after the producing
+// launch, so the sum is latency-bound: 16 waves issue all their loads (up to 16 per lane) before
+// the first add, which takes one memory round trip instead of one per load.
+constexpr int kFinWG = 1024;
+constexpr int kFinUnroll = 16;
+__global__ __launch_bounds__(kFinWG) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
+                                                     int aux_wg, double* hist, int hist_stride) {
+  __shared__ double lds[3 * (kFinWG / kWave)];
   const int slot = blockIdx.x;
   int p = 0;
   while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
@@ -305,9 +310,18 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B, int what, int kind, i
     // the first kind comes from a launch of producer_wg sites per block, the others from aux_wg
     const int ntiles = ceil_div(B.probs[p].g.half, k == 0 ? producer_wg : aux_wg);
     const double* src = B.partial + ((long)slot * kPartialSlots + kind + k) * B.pstride;
-    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s[k] += src[i];
+    double v[kFinUnroll];
+    for (int base = 0; base < ntiles; base += kFinUnroll * kFinWG) {
+#pragma unroll
+      for (int j = 0; j < kFinUnroll; ++j) {
+        const int i = base + j * kFinWG + threadIdx.x;
+        v[j] = i < ntiles ? src[i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kFinUnroll; ++j) s[k] += v[j];
+    }
   }
-  block_sum<3>(s, lds);
+  block_sum<3, kFinWG / kWave>(s, lds);
   if (threadIdx.x != 0) return;
   const double sum = s[0];
   Scal& sc = B.scal[slot];
@@ -537,7 +551,7 @@ hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, in
                            int hist_stride, hipStream_t st, int aux_wg) {
   if (bh.nslots == 0) return hipSuccess;
   const Batch B = make_batch(bh, producer_wg, 1);
-  k_finalize<<<bh.nslots, 256, 0, st>>>(B, what, kind, gate, producer_wg, aux_wg > 0 ? aux_wg : producer_wg, hist,
+  k_finalize<<<bh.nslots, kFinWG, 0, st>>>(B, what, kind, gate, producer_wg, aux_wg > 0 ? aux_wg : producer_wg, hist,
                                         hist_stride);
   return hipGetLastError();
 }

@@ -191,6 +191,126 @@ template <> __device__ __forceinline__ void load_link_rows<P16, 2>(const char* s
   u[5] = unpack_h2(t.y, s);
 }
 
+// ---- raw (undecoded) loads for software-pipelined kernels ---------------------------------
+// The loaded registers are decoded only where they are used, so a load issued several links
+// ahead is not waited for until then.
+template <int P> struct RawLink;
+template <> struct RawLink<P64> { d2v e[9]; };
+template <> struct RawLink<P32> { f4v q[4]; f2v t; };
+template <> struct RawLink<P16> { u4v q0, q1; unsigned t; };
+
+template <int P, int ROWS> __device__ __forceinline__ void raw_link_load(const char* slot, int lane, RawLink<P>& r);
+template <> __device__ __forceinline__ void raw_link_load<P64, 3>(const char* slot, int lane, RawLink<P64>& r) {
+  gptr<d2v> p = as_global<d2v>(slot) + lane;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) r.e[e] = __builtin_nontemporal_load(p + e * kWave);
+}
+template <> __device__ __forceinline__ void raw_link_load<P64, 2>(const char* slot, int lane, RawLink<P64>& r) {
+  gptr<d2v> p = as_global<d2v>(slot) + lane;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) r.e[e] = __builtin_nontemporal_load(p + e * kWave);
+}
+template <> __device__ __forceinline__ void raw_link_load<P32, 3>(const char* slot, int lane, RawLink<P32>& r) {
+  gptr<f4v> p = as_global<f4v>(slot) + lane;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r.q[j] = __builtin_nontemporal_load(p + j * kWave);
+  r.t = __builtin_nontemporal_load(as_global<f2v>(slot + 4 * kWave * 16) + lane);
+}
+template <> __device__ __forceinline__ void raw_link_load<P32, 2>(const char* slot, int lane, RawLink<P32>& r) {
+  gptr<f4v> p = as_global<f4v>(slot) + lane;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) r.q[j] = __builtin_nontemporal_load(p + j * kWave);
+}
+template <> __device__ __forceinline__ void raw_link_load<P16, 3>(const char* slot, int lane, RawLink<P16>& r) {
+  gptr<u4v> p = as_global<u4v>(slot) + lane;
+  r.q0 = __builtin_nontemporal_load(p);
+  r.q1 = __builtin_nontemporal_load(p + kWave);
+  r.t = __builtin_nontemporal_load(as_global<unsigned>(slot + 2 * kWave * 16) + lane);
+}
+template <> __device__ __forceinline__ void raw_link_load<P16, 2>(const char* slot, int lane, RawLink<P16>& r) {
+  r.q0 = __builtin_nontemporal_load(as_global<u4v>(slot) + lane);
+  const u2v t = __builtin_nontemporal_load(as_global<u2v>(slot + kWave * 16) + lane);
+  r.q1.x = t.x;
+  r.q1.y = t.y;
+}
+
+template <int P, int ROWS>
+__device__ __forceinline__ void raw_link_decode(const RawLink<P>& r, float scale, Cx<typename RealOf<P>::T> u[9]);
+template <> __device__ __forceinline__ void raw_link_decode<P64, 3>(const RawLink<P64>& r, float, Cx<double> u[9]) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = Cx<double>{r.e[e].x, r.e[e].y};
+}
+template <> __device__ __forceinline__ void raw_link_decode<P64, 2>(const RawLink<P64>& r, float, Cx<double> u[9]) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) u[e] = Cx<double>{r.e[e].x, r.e[e].y};
+}
+template <> __device__ __forceinline__ void raw_link_decode<P32, 3>(const RawLink<P32>& r, float, Cx<float> u[9]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    u[2 * j] = Cx<float>{r.q[j].x, r.q[j].y};
+    u[2 * j + 1] = Cx<float>{r.q[j].z, r.q[j].w};
+  }
+  u[8] = Cx<float>{r.t.x, r.t.y};
+}
+template <> __device__ __forceinline__ void raw_link_decode<P32, 2>(const RawLink<P32>& r, float, Cx<float> u[9]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    u[2 * j] = Cx<float>{r.q[j].x, r.q[j].y};
+    u[2 * j + 1] = Cx<float>{r.q[j].z, r.q[j].w};
+  }
+}
+template <> __device__ __forceinline__ void raw_link_decode<P16, 3>(const RawLink<P16>& r, float s, Cx<float> u[9]) {
+  u[0] = unpack_h2(r.q0.x, s);
+  u[1] = unpack_h2(r.q0.y, s);
+  u[2] = unpack_h2(r.q0.z, s);
+  u[3] = unpack_h2(r.q0.w, s);
+  u[4] = unpack_h2(r.q1.x, s);
+  u[5] = unpack_h2(r.q1.y, s);
+  u[6] = unpack_h2(r.q1.z, s);
+  u[7] = unpack_h2(r.q1.w, s);
+  u[8] = unpack_h2(r.t, s);
+}
+template <> __device__ __forceinline__ void raw_link_decode<P16, 2>(const RawLink<P16>& r, float s, Cx<float> u[9]) {
+  u[0] = unpack_h2(r.q0.x, s);
+  u[1] = unpack_h2(r.q0.y, s);
+  u[2] = unpack_h2(r.q0.z, s);
+  u[3] = unpack_h2(r.q0.w, s);
+  u[4] = unpack_h2(r.q1.x, s);
+  u[5] = unpack_h2(r.q1.y, s);
+}
+
+template <int P> struct RawSpinor;
+template <> struct RawSpinor<P64> { d2v c[3]; };
+template <> struct RawSpinor<P32> { f2v c[3]; };
+template <> struct RawSpinor<P16> { u4v w; };
+
+template <int P> __device__ __forceinline__ void raw_spinor_load(const void* base, long s, RawSpinor<P>& r);
+template <> __device__ __forceinline__ void raw_spinor_load<P64>(const void* base, long s, RawSpinor<P64>& r) {
+  gptr<d2v> p = as_global<d2v>(base) + 3 * s;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r.c[c] = p[c];
+}
+template <> __device__ __forceinline__ void raw_spinor_load<P32>(const void* base, long s, RawSpinor<P32>& r) {
+  gptr<f2v> p = as_global<f2v>(base) + 3 * s;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r.c[c] = p[c];
+}
+template <> __device__ __forceinline__ void raw_spinor_load<P16>(const void* base, long s, RawSpinor<P16>& r) {
+  r.w = as_global<u4v>(base)[s];
+}
+template <int P>
+__device__ __forceinline__ void raw_spinor_decode(const RawSpinor<P>& r, Cx<typename RealOf<P>::T> v[3]) {
+  if constexpr (P == P16) {
+    const float sc = __uint_as_float(r.w.w);
+    v[0] = unpack_h2(r.w.x, sc);
+    v[1] = unpack_h2(r.w.y, sc);
+    v[2] = unpack_h2(r.w.z, sc);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = {r.c[c].x, r.c[c].y};
+  }
+}
+
 // Third row of s U for U in SU(3) from its first two rows a' = s a, b' = s b (paper Sec. 3.3,
 // c = (a x b)^*):  s c = (a' x b')^* / s.
 template <typename T>
@@ -269,7 +389,8 @@ __device__ __forceinline__ int long_sign(const Site& s, const Geo& g, int mu, bo
 
 // ---- reductions ---------------------------------------------------------------
 // Deterministic block sum of N doubles per thread; the result is valid in thread 0.
-template <int N> __device__ __forceinline__ void block_sum(double v[N], double* lds /* >= N * 4 */) {
+template <int N, int MAXW = 4>
+__device__ __forceinline__ void block_sum(double v[N], double* lds /* >= N * MAXW */) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1)
 #pragma unroll
@@ -280,13 +401,13 @@ template <int N> __device__ __forceinline__ void block_sum(double v[N], double* 
   __syncthreads();
   if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < N; ++i) lds[i * 4 + wave] = v[i];
+    for (int i = 0; i < N; ++i) lds[i * MAXW + wave] = v[i];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      double s = lds[i * 4];
-      for (int w = 1; w < nw; ++w) s += lds[i * 4 + w];
+      double s = lds[i * MAXW];
+      for (int w = 1; w < nw; ++w) s += lds[i * MAXW + w];
       v[i] = s;
     }
 }

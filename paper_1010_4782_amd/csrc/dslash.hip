@@ -13,7 +13,26 @@
 
 namespace stag {
 
-template <int P, int R, int EPI, bool C12>
+// Issue the loads of link k of this lane's site and of the colour vector it multiplies.
+template <int P, bool C12>
+__device__ __forceinline__ void dslash_issue(int k, const Site& s, const Geo& g, const char* lbase, long blk, int lane,
+                                             const char* in, RawLink<P>& l, RawSpinor<P>& v) {
+  const int mu = k >> 2, j = k & 3;
+  const int nb = neighbour(s, g, mu, j < 2 ? g.h1[mu] : g.h3[mu], (j & 1) == 0);
+  const char* slot = lbase + link_slot_offset(P, C12, blk, k);
+  if (C12 && j >= 2)
+    raw_link_load<P, 2>(slot, lane, l);
+  else
+    raw_link_load<P, 3>(slot, lane, l);
+  raw_spinor_load<P>(in, nb, v);
+}
+
+// Prefetch distance (links) of the single right-hand-side kernel, per storage precision, from a
+// sweep of 0-16 on the 28^3x96 lattice: the compiler's own schedule keeps 2-4 loads in flight,
+// and these distances are 6% (f16), 8% (f32) and 9% (f64) faster.
+template <int P> constexpr int dslash_pf() { return P == P16 ? 12 : (P == P32 ? 8 : 6); }
+
+template <int P, int R, int EPI, bool C12, int PF>
 __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
                                                    int b_id, int gate) {
   using T = typename RealOf<P>::T;
@@ -60,6 +79,33 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] = Cx<T>{T(0), T(0)};
 
+  if constexpr (PF > 0) {
+    // Software pipeline over the 16 links: the loads of link k + PF are issued while link k is
+    // multiplied.  An empty volatile asm that takes the accumulators closes each stage: the
+    // products of link k must be done before it and the loads issued after it cannot move above
+    // it, so the compiler can neither hoist all loads to the top nor sink them to their uses.
+    static_assert(R == 1, "the pipelined path serves one right-hand side per lane");
+    RawLink<P> lb[PF];
+    RawSpinor<P> vb[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) dslash_issue<P, C12>(k, s, g, lbase, blk, lane, in, lb[k], vb[k]);
+#pragma unroll
+    for (int k = 0; k < kLinks; ++k) {
+      const int mu = k >> 2, j = k & 3;
+      Cx<T> u[9], v[3];
+      if (C12 && j >= 2) {
+        raw_link_decode<P, 2>(lb[k % PF], sc_long, u);
+        rebuild_row3(u, (T)(long_sign(s, g, mu, j == 2) * g.cn_inv));
+      } else {
+        raw_link_decode<P, 3>(lb[k % PF], j < 2 ? sc_fat : sc_long, u);
+      }
+      raw_spinor_decode<P>(vb[k % PF], v);
+      matvec_acc(u, v, acc[0]);
+      if (k + PF < kLinks) dslash_issue<P, C12>(k + PF, s, g, lbase, blk, lane, in, lb[k % PF], vb[k % PF]);
+      asm volatile("" : "+v"(acc[0][0].re), "+v"(acc[0][0].im), "+v"(acc[0][1].re), "+v"(acc[0][1].im),
+                   "+v"(acc[0][2].re), "+v"(acc[0][2].im));
+    }
+  } else
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -147,20 +193,22 @@ Batch make_batch(const BatchHost& bh, int wg, int r) {
 template <int P, int R, bool C12>
 static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                            int gate, int wg, hipStream_t st) {
+  constexpr int PF = R == 1 ? dslash_pf<P>() : 0;
+  constexpr int PF64 = R == 1 ? dslash_pf<P64>() : 0;
   switch (epi) {
     case EPI_PLAIN:
-      k_dslash<P, R, EPI_PLAIN, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_PLAIN, C12, PF><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_XPAY_DOT:
-      k_dslash<P, R, EPI_XPAY_DOT, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_XPAY_DOT, C12, PF><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_RESID:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_RESID, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_RESID, C12, PF64><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_XPAY:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_XPAY, C12><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_XPAY, C12, PF64><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     default:
       return hipErrorInvalidValue;

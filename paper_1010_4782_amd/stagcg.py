@@ -48,7 +48,8 @@ def solve_params(tol=1e-10, prec="f64", max_iter=0, reliable_interval=50, reliab
     p.reliable_delta = reliable_delta
     p.check_interval = check_interval
     p.max_restarts = max_restarts
-    p.profile = 1 if profile else 0
+    # profile: False/0 off, True = every iteration, k > 1 = every k-th iteration
+    p.profile = int(profile) if not isinstance(profile, bool) else (1 if profile else 0)
     p.history_len = history_len
     if history is not None:
         p.history = history.ctypes.data_as(C.POINTER(C.c_double))
