@@ -90,15 +90,17 @@ def copy_ceiling(torch, nbytes=2 << 30, reps=10):
             "avg_launch_us": ms * 1e3}
 
 
-def measured_traffic(prec: str, dims):
+def measured_traffic(prec: str, dims, long_su3: bool):
     """HBM bytes per Dslash launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source and this workload; otherwise None."""
+    current kernel source, this workload and this long-link storage; otherwise None."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec.get("long_su3", False) != long_su3:
+        return None
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -302,7 +304,7 @@ def main(argv=None):
         "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(a.prec, d0) if len(probs) == 1 and probs[0]["nrhs"] == 1 else None,
+                     "traffic": measured_traffic(a.prec, d0, not a.no_long_su3) if len(probs) == 1 and probs[0]["nrhs"] == 1 else None,
                      "kernel": f"k_dslash<{a.prec}> (plain and xpay launches)",
                      "avg_launch_us": avg_ms * 1e3, "launches": d_calls, "bytes_per_launch": bytes_per_launch},
     }
