@@ -93,6 +93,87 @@ __global__ __launch_bounds__(256) void k_net_layer(NetLayerArgs a) {
   for (int c = 0; c < COUT; ++c) store_spinor<P32>(a.out + (long)c * a.g.half * 3, cb, acc[c]);
 }
 
+// Channel mixing on the matrix cores.  For the 64 sites of one wave and one term d (identity or a
+// transport), the mixing is the complex product Y[c][n] += sum_c' W_d[c][c'] X_d[c'][n] over the
+// 192 columns n = 3 site + colour.  It runs as a real GEMM with the 2x2 real form of each complex
+// weight: rows i = 2c + {re, im}, inner index k = 2c' + {re, im},
+//   A[2c][2c'] = Re W, A[2c][2c'+1] = -Im W, A[2c+1][2c'] = Im W, A[2c+1][2c'+1] = Re W,
+// on v_mfma_f32_16x16x4_f32 (A 16x4, B 4x16, C 16x16 in FP32): twelve 16-column tiles, and
+// ceil(CIN/2) steps of 4 inner indices per term.  The transports stay on the vector units, one
+// lane per site, and reach the MFMA operand layout through LDS (12 KB per wave for CIN = 8).
+//   MFMA lane layout (16x16x4): lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
+//   C[4 (l / 16) + r][l % 16], r = 0..3.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_net_layer_mfma(NetLayerArgs a) {
+  static_assert(CIN >= 2 && CIN <= 8 && COUT >= 2 && COUT <= 8, "the matrix-core layer needs 2..8 channels");
+  constexpr int KS = (CIN + 1) / 2;  // inner steps of 4 reals (2 input channels) per term
+  constexpr int NT = 3 * kWave / 16;  // 16-column tiles per wave
+  __shared__ float2 xs[256 / kWave][CIN][3 * kWave];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int cb_raw = blockIdx.x * blockDim.x + threadIdx.x;
+  const int wave_base = cb_raw - lane;
+  if (wave_base >= a.g.half) return;  // whole wave past the lattice (uniform per wave)
+  const bool live = cb_raw < a.g.half;
+  const int cb = live ? cb_raw : a.g.half - 1;  // dead lanes compute a valid site; their columns are not stored
+  const Site s = site_of(cb, a.out_par, a.g);
+  const int row = lane & 15, kq = lane >> 4;
+  f4v acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+  float* xw = reinterpret_cast<float*>(&xs[wave][0][0]);
+#pragma unroll 1
+  for (int d = 0; d < 9; ++d) {
+    if (d == 0 ? a.in_same == nullptr : a.in_other == nullptr) continue;  // uniform
+    Cx<float> t[CIN][3];
+    if (d == 0) {
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+    } else {
+      transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
+    }
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) xs[wave][ci][3 * lane + i] = make_float2(t[ci][i].re, t[ci][i].im);
+    __builtin_amdgcn_wave_barrier();
+    // A operand of this lane: row `row`, inner index 4 ks + kq
+    float av[KS];
+    {
+      const int c = row >> 1, ri = row & 1;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + kq, cp = k >> 1, ki = k & 1;
+        float v = 0.f;
+        if (c < COUT && cp < CIN) {
+          const float2 w = a.w[(d * COUT + c) * CIN + cp];
+          v = ri == 0 ? (ki == 0 ? w.x : -w.y) : (ki == 0 ? w.y : w.x);
+        }
+        av[ks] = v;
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cp = 2 * ks + (kq >> 1), ki = kq & 1;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const float bv = cp < CIN ? xw[(cp * 3 * kWave + 16 * j + row) * 2 + ki] : 0.f;
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bv, acc[j], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // C rows 4 kq .. 4 kq + 3 are channels 2 kq and 2 kq + 1, (re, im) each; column 16 j + row.
+  const int c0 = 2 * kq;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int n = 16 * j + row;
+    const int site = wave_base + n / 3, colour = n % 3;
+    if (site >= a.g.half) continue;
+    if (c0 < COUT) a.out[((long)c0 * a.g.half + site) * 3 + colour] = make_float2(acc[j][0], acc[j][1]);
+    if (c0 + 1 < COUT) a.out[((long)(c0 + 1) * a.g.half + site) * 3 + colour] = make_float2(acc[j][2], acc[j][3]);
+  }
+}
+
 // Weight gradient, one direction d (blockIdx.y) and a group of G output channels (blockIdx.z):
 //   partial[p][d][c][c'] = sum_n sum_a G_c(n)_a conj((T_d psi_c')(n)_a)
 // over the output sites of parity a.out_par; each block walks sites with a grid stride and
@@ -150,6 +231,96 @@ __global__ __launch_bounds__(256) void k_net_wgrad(NetLayerArgs a, const float2*
       }
       __syncthreads();
     }
+}
+
+// Weight gradient on the matrix cores, one direction d per blockIdx.y:
+//   P[c][c'] = sum_n sum_a G_c(n)_a conj(X_d,c'(n)_a),  X_d = T_d psi (or psi for d = 0),
+// as a real GEMM over the inner index k = 2 n + part (n = 3 site + colour) with rows i = 2c + {re, im}:
+//   A[2c][(n,0)] = Re G, A[2c][(n,1)] = Im G, A[2c+1][(n,0)] = Im G, A[2c+1][(n,1)] = -Re G,
+//   B[(n,0)][c'] = Re X, B[(n,1)][c'] = Im X   (columns c' >= CIN are zero).
+// Each wave walks 64-site chunks with a grid stride and accumulates one 16x16 FP32 tile; the waves
+// of a block are summed in FP64 in a fixed order and written as one partial per block in the
+// layout of k_net_wgrad.
+constexpr int kWgradMfmaWG = 128;  // two waves: 52 KB of LDS per workgroup at 8 channels, three per CU
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kWgradMfmaWG) void k_net_wgrad_mfma(NetLayerArgs a, const float2* gy, double* partial) {
+  static_assert(CIN >= 2 && CIN <= 8 && COUT >= 2 && COUT <= 8, "the matrix-core gradient needs 2..8 channels");
+  constexpr int NW = kWgradMfmaWG / kWave;
+  __shared__ float2 xs[NW][CIN][3 * kWave];
+  __shared__ float2 gs[NW][COUT][3 * kWave];
+  __shared__ double red[NW][kWave][4];
+  const int d = blockIdx.y;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int row = lane & 15, kq = lane >> 4;
+  f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+  const bool have = d == 0 ? a.in_same != nullptr : a.in_other != nullptr;
+  const float* xw = reinterpret_cast<const float*>(&xs[wave][0][0]);
+  const float* gw = reinterpret_cast<const float*>(&gs[wave][0][0]);
+  if (have && gy) {
+    const int nchunk = ceil_div(a.g.half, kWave);
+    for (int ch = blockIdx.x * NW + wave; ch < nchunk; ch += gridDim.x * NW) {  // uniform per wave
+      const int cb_raw = ch * kWave + lane;
+      const bool live = cb_raw < a.g.half;
+      const int cb = live ? cb_raw : a.g.half - 1;
+      Cx<float> t[CIN][3];
+      if (d == 0) {
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+      } else {
+        const Site s = site_of(cb, a.out_par, a.g);
+        transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
+      }
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          xs[wave][ci][3 * lane + i] = live ? make_float2(t[ci][i].re, t[ci][i].im) : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < COUT; ++c) {
+        Cx<float> gv[3];
+        load_spinor<P32>(gy + (long)c * a.g.half * 3, cb, gv);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) gs[wave][c][3 * lane + i] = live ? make_float2(gv[i].re, gv[i].im) : make_float2(0.f, 0.f);
+      }
+      __builtin_amdgcn_wave_barrier();
+      // inner step ks covers n = 2 ks + (kq >> 1), part = kq & 1
+      const int c = row >> 1, ri = row & 1, part = kq & 1;
+#pragma unroll 8
+      for (int ks = 0; ks < 3 * kWave / 2; ++ks) {
+        const int n = 2 * ks + (kq >> 1);
+        float av = 0.f, bv = 0.f;
+        if (c < COUT) {
+          const float gr = gw[(c * 3 * kWave + n) * 2], gi = gw[(c * 3 * kWave + n) * 2 + 1];
+          av = ri == 0 ? (part == 0 ? gr : gi) : (part == 0 ? gi : -gr);
+        }
+        if (row < CIN) bv = xw[(row * 3 * kWave + n) * 2 + part];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave][lane][r] = (double)acc[r];
+  __syncthreads();
+  if (wave != 0) return;
+  double v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v[r] = red[0][lane][r];
+    for (int w = 1; w < NW; ++w) v[r] += red[w][lane][r];
+  }
+  // C rows 4 kq + r: channel 2 kq + (r >> 1), part r & 1; column row = c'
+  const int cp = row;
+  if (cp >= CIN) return;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int co = 2 * kq + h;
+    if (co >= COUT) continue;
+    const long idx = ((((long)a.out_par * 9 + d) * COUT + co) * CIN + cp) * gridDim.x + blockIdx.x;
+    partial[2 * idx] = v[2 * h];
+    partial[2 * idx + 1] = v[2 * h + 1];
+  }
 }
 
 // out[d][c][c'] = sum over parities and blocks of the partials, in a fixed order.
@@ -213,12 +384,17 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* partial, int
 // ---- launchers ---------------------------------------------------------------------
 hipError_t launch_net_layer(const NetLayerArgs& a, int cin, int cout, hipStream_t st) {
   const int nb = ceil_div(a.g.half, 256);
+  // layers with at least two channels on both sides mix on the matrix cores; 1 -> C and C -> 1
+  // would fill at most a quarter of an MFMA tile and stay on the vector units
 #define STAG_NET_LAYER(I, O) \
   if (cin == I && cout == O) { k_net_layer<I, O><<<nb, 256, 0, st>>>(a); return hipGetLastError(); }
-  STAG_NET_LAYER(1, 1) STAG_NET_LAYER(1, 2) STAG_NET_LAYER(2, 1) STAG_NET_LAYER(2, 2)
-  STAG_NET_LAYER(1, 4) STAG_NET_LAYER(4, 1) STAG_NET_LAYER(4, 4)
-  STAG_NET_LAYER(1, 8) STAG_NET_LAYER(8, 1) STAG_NET_LAYER(8, 8)
+#define STAG_NET_LAYER_MFMA(I, O) \
+  if (cin == I && cout == O) { k_net_layer_mfma<I, O><<<nb, 256, 0, st>>>(a); return hipGetLastError(); }
+  STAG_NET_LAYER(1, 1) STAG_NET_LAYER(1, 2) STAG_NET_LAYER(2, 1) STAG_NET_LAYER_MFMA(2, 2)
+  STAG_NET_LAYER(1, 4) STAG_NET_LAYER(4, 1) STAG_NET_LAYER_MFMA(4, 4)
+  STAG_NET_LAYER(1, 8) STAG_NET_LAYER(8, 1) STAG_NET_LAYER_MFMA(8, 8)
 #undef STAG_NET_LAYER
+#undef STAG_NET_LAYER_MFMA
   return hipErrorInvalidValue;
 }
 
@@ -229,10 +405,16 @@ hipError_t launch_net_wgrad(const NetLayerArgs& a, const float2* gy, double* par
     k_net_wgrad<I, O, G><<<dim3(nblk, 9, O / G), 256, 0, st>>>(a, gy, partial); \
     return hipGetLastError();                                                 \
   }
-  STAG_NET_WG(1, 1, 1) STAG_NET_WG(1, 2, 2) STAG_NET_WG(2, 1, 1) STAG_NET_WG(2, 2, 2)
-  STAG_NET_WG(1, 4, 4) STAG_NET_WG(4, 1, 1) STAG_NET_WG(4, 4, 4)
-  STAG_NET_WG(1, 8, 8) STAG_NET_WG(8, 1, 1) STAG_NET_WG(8, 8, 4)
+#define STAG_NET_WG_MFMA(I, O)                                                       \
+  if (cin == I && cout == O) {                                                       \
+    k_net_wgrad_mfma<I, O><<<dim3(nblk, 9, 1), kWgradMfmaWG, 0, st>>>(a, gy, partial); \
+    return hipGetLastError();                                                        \
+  }
+  STAG_NET_WG(1, 1, 1) STAG_NET_WG(1, 2, 2) STAG_NET_WG(2, 1, 1) STAG_NET_WG_MFMA(2, 2)
+  STAG_NET_WG(1, 4, 4) STAG_NET_WG(4, 1, 1) STAG_NET_WG_MFMA(4, 4)
+  STAG_NET_WG(1, 8, 8) STAG_NET_WG(8, 1, 1) STAG_NET_WG_MFMA(8, 8)
 #undef STAG_NET_WG
+#undef STAG_NET_WG_MFMA
   return hipErrorInvalidValue;
 }
 

@@ -53,14 +53,16 @@ def test_net_forward_matches_oracle(gpu_lib, dims, channels):
         assert rel(out[k], ref) <= 2e-5
 
 
-def test_net_loss_and_gradients_match_oracle(gpu_lib):
+@pytest.mark.parametrize("dims,width", [((4, 4, 2, 6), 4), ((6, 4, 2, 6), 8)])
+def test_net_loss_and_gradients_match_oracle(gpu_lib, dims, width):
+    """Loss and weight gradients; widths 4 and 8 run the matrix-core layer and gradient kernels
+    (6x4x2x6: 144 sites per parity, a ragged last wave)."""
     from paper_1010_4782_amd.stagcg import Net
 
-    print("net loss/grad", flush=True)
-    dims = (4, 4, 2, 6)
+    print(f"net loss/grad {dims} width {width}", flush=True)
     lat, fat, _ = setup(dims, 7)
-    channels = [1, 4, 4, 1]
-    net = Net(lat, layers=3, channels=4)
+    channels = [1, width, width, 1]
+    net = Net(lat, layers=3, channels=width)
     W32 = [quant.to_f32(w) for w in init_weights(channels, 8, scale=1.0)]
     net.set_weights(W32)
     b = gaussian_source(dims, 9, 3)
