@@ -335,3 +335,35 @@ def test_cg_with_twelve_parameter_long_links(gpu_lib, prec):
     x, info = lat.cg_solve(torch.from_numpy(b).cuda(), m, prec=prec)
     assert info[0]["converged"] == 1
     assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[0], x.cpu().numpy()[0]) <= 1.05e-10
+
+
+def test_profile_samples_every_kth_iteration(gpu_lib):
+    """profile = k brackets the Dslash pair of every k-th iteration: 2 launches per sampled iteration."""
+    lat, fat, lng = make((6, 6, 6, 6), seed=111, precs=("f64",))
+    b = torch.from_numpy(gaussian_source((6, 6, 6, 6), 112)).cuda()
+    print("profile sampling", flush=True)
+    _, info1 = lat.cg_solve(b, 0.1, tol=1e-10, profile=1)
+    _, info5 = lat.cg_solve(b, 0.1, tol=1e-10, profile=5)
+    _, info0 = lat.cg_solve(b, 0.1, tol=1e-10, profile=0)
+    it = info1[0]["iters"]
+    assert info1[0]["iters"] == info5[0]["iters"] == info0[0]["iters"]  # timing does not change the solve
+    # iterations are launched in chunks of 16 between polls, so up to 15 launched after convergence
+    # may be sampled too (on a lattice this small they are not told apart from working ones)
+    for k, info in ((1, info1), (5, info5)):
+        lo, hi = 2 * (-(-it // k)) - 4, 2 * (-(-(it + 15) // k)) + 4
+        assert lo <= info[0]["dslash_calls"] <= hi, (k, it, info[0]["dslash_calls"])
+    assert info0[0]["dslash_calls"] == 0 and info0[0]["dslash_ms"] == 0.0
+    assert info1[0]["dslash_ms"] > 0 and info5[0]["dslash_ms"] > 0
+
+
+def test_batch_rejects_mixed_long_link_storage(gpu_lib):
+    """One launch per stage serves every lattice of a batch, so their three-hop storage must agree."""
+    from paper_1010_4782_amd.stagcg import StagError, cg_solve_batch
+
+    print("mixed long-link batch", flush=True)
+    dims = (4, 4, 4, 4)
+    lat_a, _, _ = make(dims, seed=121, precs=("f64",))
+    lat_b, _, _ = make12(dims, 123, ("f64",))
+    b = torch.from_numpy(gaussian_source(dims, 125)).cuda()
+    with pytest.raises(StagError):
+        cg_solve_batch([(lat_a, b, [0.1], None), (lat_b, b, [0.1], None)], tol=1e-10)
