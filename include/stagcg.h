@@ -62,7 +62,8 @@ typedef enum { STAG_F64 = 0, STAG_F32 = 1, STAG_F16 = 2 } stag_prec;
 #define STAG_PREC_BIT(p) (1u << (p))
 /* stag_load_links flag: the three-hop links are SU(3) matrices; store two rows each (12 real
  * parameters) and rebuild the third as (a x b)^* (Sec. 3.3, Eq. SU3rec), which moves 16% fewer bytes
- * per Dslash.  Only correct for special unitary long links. */
+ * per Dslash.  Only correct for special unitary long links; needs lng != NULL and naik_coeff != 0
+ * (STAG_ERR_ARG otherwise). */
 #define STAG_LONG_SU3 (1u << 8)
 
 typedef enum { STAG_PRECOND_NONE = 0, STAG_PRECOND_NET = 1 } stag_precond;
@@ -81,7 +82,9 @@ typedef struct {
   int32_t precond;           /* stag_precond; STAG_PRECOND_NET runs flexible CG (single problem only) with the
                                 network as preconditioner, then plain CG if it stalls or breaks down */
   stag_net_t net;            /* network for STAG_PRECOND_NET (built on the solve's lattice) */
-  int32_t stall_window;      /* FCG: fall back to plain CG if ||r_k|| > stall_ratio ||r_{k-w}|| (default 10) */
+  int32_t stall_window;      /* FCG: every stall_window iterations (default 10) the smallest ||r|| seen so far
+                                is compared with the smallest seen one window earlier; if it did not fall
+                                below stall_ratio times that value, plain CG finishes from the current x */
   double stall_ratio;        /* default 0.9 */
   int32_t profile;           /* k > 0: time the Dslash launches of every k-th inner iteration with HIP events
                                 (stag_cg_info.dslash_ms); each timed iteration idles the GPU for a few us
@@ -175,7 +178,10 @@ stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b,
 
 /* Solve several problems (lattices of different shapes, each with its own
  * right-hand sides and masses) as one batch: every CG stage is one launch over
- * all problems.  probs: host [nprob]; info: host [sum of nrhs], in problem order. */
+ * all problems.  probs: host [nprob], nprob <= 16, each lattice at most once (merge its
+ * right-hand sides), all with the same long-link storage (STAG_LONG_SU3 or not);
+ * info: host [sum of nrhs], in problem order.  Network preconditioning is for
+ * single-problem solves only. */
 stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const stag_cg_params* prm,
                                 stag_cg_info* info, void* stream);
 

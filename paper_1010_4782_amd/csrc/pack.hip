@@ -88,7 +88,9 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
       const int grp = (k >> 1) & 1;
       const int nst = (c12 && grp) ? 6 : 9;  // stored entries (two rows of a compressed three-hop link)
       double m = 0.0;
-      for (int e = 0; e < nst; ++e) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
+#pragma unroll
+      for (int e = 0; e < 9; ++e)  // fixed trip count: u stays in registers
+        if (e < nst) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
       scale[grp] = fmaxf(scale[grp], (float)m);  // float rounding of a max equals the max of the roundings
     }
     lscale[blk * 2 * kWave + lane] = scale[0];
@@ -106,11 +108,15 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
     const bool two_rows = c12 && ((k & 3) >= 2);
     if (P == P64) {
       double2* o = reinterpret_cast<double2*>(base) + lane;
-      for (int e = 0; e < (two_rows ? 6 : 9); ++e) o[e * kWave] = u[e];
+#pragma unroll
+      for (int e = 0; e < 9; ++e)
+        if (e < (two_rows ? 6 : 9)) o[e * kWave] = u[e];
     } else if (P == P32) {
       float4* o = reinterpret_cast<float4*>(base) + lane;
-      for (int j = 0; j < (two_rows ? 3 : 4); ++j)
-        o[j * kWave] = make_float4((float)u[2 * j].x, (float)u[2 * j].y, (float)u[2 * j + 1].x, (float)u[2 * j + 1].y);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < (two_rows ? 3 : 4))
+          o[j * kWave] = make_float4((float)u[2 * j].x, (float)u[2 * j].y, (float)u[2 * j + 1].x, (float)u[2 * j + 1].y);
       if (!two_rows) reinterpret_cast<float2*>(base + 4 * kWave * 16)[lane] = make_float2((float)u[8].x, (float)u[8].y);
     } else {
       const float sc = scale[(k >> 1) & 1];
