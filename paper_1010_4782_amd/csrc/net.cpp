@@ -227,6 +227,23 @@ stag_status net_arg(const char* m) {
   return STAG_ERR_ARG;
 }
 
+}  // namespace
+
+// The transports read the lattice's FP32 links at every launch: they must still be loaded (a later
+// stag_load_links may have dropped them), and the lattice's device must be current.
+stag_status stag::net_check(stag_net_s* n) {
+  const stag_lattice_s* lat = n->lat;
+  if (!lat->loaded || !(lat->built & STAG_PREC_BIT(STAG_F32)) || !lat->links[P32][0].ptr) {
+    set_error("the network transports need the lattice's FP32 links: load them with STAG_PREC_BIT(STAG_F32)");
+    return STAG_ERR_STATE;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != lat->device) return net_arg("the current HIP device is not the lattice's device");
+  return STAG_OK;
+}
+
+namespace {
+
 hipError_t net_alloc(stag_net_s* n) {
   const size_t half = n->lat->g.half;
   const int cmax = *std::max_element(n->ch.begin(), n->ch.end());
@@ -292,6 +309,19 @@ stag_status loss_grad(stag_net_s* n, const char* b, const char* x, const std::ve
 
 }  // namespace
 
+// No exception may cross the C ABI.
+#define STAG_NET_GUARD_BEGIN try {
+#define STAG_NET_GUARD_END                                    \
+  }                                                           \
+  catch (const std::bad_alloc&) {                             \
+    set_error("host allocation failed");                      \
+    return STAG_ERR_NOMEM;                                    \
+  }                                                           \
+  catch (const std::exception& ex) {                          \
+    set_error(std::string("internal error: ") + ex.what());   \
+    return STAG_ERR_STATE;                                    \
+  }
+
 extern "C" {
 
 stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels, uint32_t flags, uint64_t seed,
@@ -341,9 +371,11 @@ stag_status stag_net_create(stag_lattice_t lat, int32_t layers, int32_t channels
 }
 
 stag_status stag_net_destroy(stag_net_t net) {
+  STAG_NET_GUARD_BEGIN
   if (!net) return net_arg("network is NULL");
   delete net;
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 stag_status stag_net_num_weights(stag_net_t net, int64_t* n_complex) {
@@ -355,6 +387,7 @@ stag_status stag_net_num_weights(stag_net_t net, int64_t* n_complex) {
 }
 
 stag_status stag_net_set_weights(stag_net_t net, const double* w, int64_t n_complex) {
+  STAG_NET_GUARD_BEGIN
   if (!net || !w) return net_arg("network and weights must not be NULL");
   int64_t t = 0;
   for (int l = 0; l < net->layers; ++l) t += nweights(net, l);
@@ -371,9 +404,11 @@ stag_status stag_net_set_weights(stag_net_t net, const double* w, int64_t n_comp
   STAG_HIP_TRY(upload_weights(net, nullptr));
   zero_adam(net);
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 stag_status stag_net_get_weights(stag_net_t net, double* w, int64_t n_complex) {
+  STAG_NET_GUARD_BEGIN
   if (!net || !w) return net_arg("network and weights must not be NULL");
   int64_t t = 0;
   for (int l = 0; l < net->layers; ++l) t += nweights(net, l);
@@ -386,25 +421,36 @@ stag_status stag_net_get_weights(stag_net_t net, double* w, int64_t n_complex) {
       ++k;
     }
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 stag_status stag_net_apply(stag_net_t net, const void* in, void* out, int32_t nrhs, void* stream) {
+  STAG_NET_GUARD_BEGIN
   if (!net || !in || !out) return net_arg("network, in and out must not be NULL");
   if (in == out) return net_arg("in and out must not overlap");
   if (nrhs < 1) return net_arg("nrhs must be >= 1");
+  stag_status s = net_check(net);
+  if (s != STAG_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t vb = (size_t)net->lat->g.half * 48;
   for (int r = 0; r < nrhs; ++r)
     STAG_HIP_TRY(net_forward(net, reinterpret_cast<const char*>(in) + r * vb, reinterpret_cast<char*>(out) + r * vb, st));
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int32_t npairs, int32_t loss_kind,
                                double mass, double* loss, double* grad, void* stream) {
+  STAG_NET_GUARD_BEGIN
   if (!net || !b || !x || !loss) return net_arg("network, b, x and loss must not be NULL");
   if (npairs < 1) return net_arg("npairs must be >= 1");
   if (loss_kind != 0 && loss_kind != 1) return net_arg("loss_kind must be 0 or 1");
   if (!std::isfinite(mass)) return net_arg("mass must be finite");
+  if (loss_kind == 1 && !(net->lat->built & STAG_PREC_BIT(STAG_F64))) return net_arg("the residual loss needs FP64 links");
+  {
+    const stag_status c = net_check(net);
+    if (c != STAG_OK) return c;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t ng = net_grad_count(net);
   STAG_HIP_TRY(hipMemsetAsync(net->gacc.ptr, 0, ng * sizeof(double), st));
@@ -418,6 +464,7 @@ stag_status stag_net_loss_grad(stag_net_t net, const void* b, const void* x, int
     STAG_HIP_TRY(hipStreamSynchronize(st));
   }
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 void stag_train_params_default(stag_train_params* p) {
@@ -436,6 +483,7 @@ void stag_train_params_default(stag_train_params* p) {
 
 stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t npairs, const stag_train_params* prm_in,
                            stag_train_info* info, void* stream) {
+  STAG_NET_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   if (!net || !b || !x) return net_arg("network, b and x must not be NULL");
   if (npairs < 1) return net_arg("npairs must be >= 1");
@@ -445,6 +493,10 @@ stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t
       !(prm.beta2 >= 0.0 && prm.beta2 < 1.0) || !(prm.eps > 0.0) || (prm.loss_kind != 0 && prm.loss_kind != 1) ||
       !std::isfinite(prm.mass))
     return net_arg("invalid training parameters");
+  {
+    const stag_status c = net_check(net);
+    if (c != STAG_OK) return c;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t ng = net_grad_count(net);
   std::vector<double> g(ng);
@@ -524,6 +576,7 @@ stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t
     info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return STAG_OK;
+  STAG_NET_GUARD_END
 }
 
 }  // extern "C"

@@ -88,6 +88,8 @@ bool load_table(const char* path, int* n_loaded);
 
 // Network (net.cpp).
 stag_lattice_s* net_lattice(stag_net_s* n);
+// STAG_OK if the network's lattice still holds FP32 links and its device is current.
+stag_status net_check(stag_net_s* n);
 hipError_t net_forward(stag_net_s* n, const void* in, void* out, hipStream_t st);
 
 // Solvers (solver.cpp).

@@ -232,6 +232,8 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     if (nprob != 1) return fail_arg("the network preconditioner solves one problem at a time");
     if (!prm.net) return fail_arg("precond = STAG_PRECOND_NET needs a network");
     if (net_lattice(prm.net) != probs[0].lat) return fail_arg("the network was built on another lattice");
+    const stag_status c = net_check(prm.net);
+    if (c != STAG_OK) return c;
     if (!(prm.stall_ratio > 0.0)) return fail_arg("stall_ratio must be positive");
   }
   if (prm.check_interval <= 0) prm.check_interval = 16;
@@ -253,6 +255,13 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     if (!q.lat->loaded) { set_error("load_links has not been called on a lattice of the batch"); return STAG_ERR_STATE; }
     if (q.nrhs < 1) return fail_arg("nrhs must be >= 1");
     if (!q.mass || !q.b || !q.x) return fail_arg("mass, b and x must not be NULL");
+    {
+      // x is rewritten while b is still read (true residual): the two may not overlap
+      const char* b0 = static_cast<const char*>(q.b);
+      const char* x0 = static_cast<const char*>(q.x);
+      const size_t bytes = (size_t)q.lat->g.half * 48 * q.nrhs;
+      if (b0 < x0 + bytes && x0 < b0 + bytes) return fail_arg("b and x must not overlap");
+    }
     if (!(q.lat->built & STAG_PREC_BIT(prm.prec))) return fail_arg("the requested precision was not packed by load_links");
     if (q.lat->device != dev) return fail_arg("lattice belongs to another device than the current one");
     if (!seen.insert(q.lat).second) return fail_arg("a lattice may appear only once per batch (merge its right-hand sides)");

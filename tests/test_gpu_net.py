@@ -162,3 +162,24 @@ def test_hermitian_network_on_gpu(gpu_lib):
     assert abs(a - b) <= 1e-5 * abs(a)
     q = torch.vdot(v.flatten(), net.apply(v).flatten()).item()
     assert q.real > 0 and abs(q.imag) <= 1e-5 * q.real
+
+
+def test_net_refuses_when_fp32_links_were_dropped(gpu_lib):
+    """The transports read the lattice's FP32 links at every launch: after a reload without them,
+    every network call returns STAG_ERR_STATE before launching anything."""
+    from paper_1010_4782_amd.stagcg import Net, StagError
+
+    print("net after link reload", flush=True)
+    dims = (4, 4, 4, 4)
+    lat, fat, lng = setup(dims, 31)
+    net = Net(lat, layers=2, channels=2)
+    b = torch.from_numpy(gaussian_source(dims, 32, 1)).cuda()
+    net.apply(b)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64",))
+    with pytest.raises(StagError) as ei:
+        net.apply(b)
+    assert ei.value.status == 4  # STAG_ERR_STATE
+    with pytest.raises(StagError):
+        lat.cg_solve(b, 0.1, tol=1e-10, net=net)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32"))
+    net.apply(b)  # usable again once the FP32 links are back

@@ -215,6 +215,18 @@ def test_argument_errors(gpu_lib):
     lat2, _, _ = make((4, 4, 4, 4))
     with pytest.raises(StagError):
         lat2.dslash(v, 0, prec="f16")           # precision not packed
+    # b and x overlapping (the binding never does this; the C ABI must refuse it)
+    import ctypes as C
+
+    from paper_1010_4782_amd._lib import StagInfo, lib
+    from paper_1010_4782_amd.stagcg import solve_params
+
+    prm = solve_params()
+    info = (StagInfo * 1)()
+    mass = (C.c_double * 1)(0.1)
+    st = lib().stag_cg_solve(lat2.handle, mass, C.c_void_p(v.data_ptr()), C.c_void_p(v.data_ptr()), 1,
+                             C.byref(prm), info, None)
+    assert st == 1  # STAG_ERR_ARG
 
 
 def test_dslash_full_size_28cubed_96_sampled(gpu_lib):
