@@ -7,8 +7,11 @@
 // one-hop matrices of the Dslash: for output parity p, k = 4 mu is F~_mu(n) and
 // k = 4 mu + 1 is -F~_mu(n-mu)^dag, so T_{-mu} = -L_{4mu+1}.
 //
-// Activations are complex64 and stored per parity: [parity][channel][V/2] x 3 colours.
-// A null input pointer stands for a field that is zero on that parity.
+// Activations are complex64, stored per parity.  With C >= 2 channels they are interleaved in
+// channel pairs, [parity][C/2][V/2][3 colours][2 channels] (48 B per pair and site, three 16-byte
+// loads), so that reading all channels of a neighbour takes 3C/2 wide loads instead of 3C narrow
+// ones; a single channel is [parity][V/2][3].  A null input pointer stands for a field that is
+// zero on that parity.
 #include "device.h"
 #include "net.h"
 #include "launch.h"
@@ -20,6 +23,42 @@ __device__ __forceinline__ void cmac_f(Cx<float>& acc, const float2 w, const Cx<
   acc.re = fmaf(-w.y, v.im, acc.re);
   acc.im = fmaf(w.x, v.im, acc.im);
   acc.im = fmaf(w.y, v.re, acc.im);
+}
+
+// Channels c0 .. c0 + G - 1 of a C-channel activation at site cb (c0 even when G >= 2).
+template <int C, int G>
+__device__ __forceinline__ void load_channels(const float2* base, long half, long cb, int c0, Cx<float> t[G][3]) {
+  if constexpr (C == 1) {
+    load_spinor<P32>(base, cb, t[0]);
+  } else {
+    static_assert(G % 2 == 0, "channel pairs are loaded whole");
+#pragma unroll
+    for (int q = 0; q < G / 2; ++q) {
+      gptr<f4v> p = as_global<f4v>(base + ((long)(c0 / 2 + q) * half + cb) * 6);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const f4v w = p[i];
+        t[2 * q][i] = Cx<float>{w.x, w.y};
+        t[2 * q + 1][i] = Cx<float>{w.z, w.w};
+      }
+    }
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void store_channels(float2* base, long half, long cb, const Cx<float> v[C][3]) {
+  if constexpr (C == 1) {
+    gptr_w<f2v> p = as_global_w<f2v>(base + cb * 3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = f2v{v[0][i].re, v[0][i].im};
+  } else {
+#pragma unroll
+    for (int q = 0; q < C / 2; ++q) {
+      gptr_w<f4v> p = as_global_w<f4v>(base + ((long)q * half + cb) * 6);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) p[i] = f4v{v[2 * q][i].re, v[2 * q][i].im, v[2 * q + 1][i].re, v[2 * q + 1][i].im};
+    }
+  }
 }
 
 // Transported colour vectors of all input channels along direction d (1..8) for the site s.
@@ -37,13 +76,13 @@ __device__ __forceinline__ void transported(const NetLayerArgs& a, const Site& s
   if (!fwd)
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = Cx<float>{-u[e].re, -u[e].im};
+  Cx<float> v[CIN][3];
+  load_channels<CIN, CIN>(a.in_other, a.g.half, nb, 0, v);
 #pragma unroll
   for (int c = 0; c < CIN; ++c) {
-    Cx<float> v[3];
-    load_spinor<P32>(a.in_other + (long)c * a.g.half * 3, nb, v);
 #pragma unroll
     for (int i = 0; i < 3; ++i) t[c][i] = Cx<float>{0.f, 0.f};
-    matvec_acc(u, v, t[c]);
+    matvec_acc(u, v[c], t[c]);
   }
 }
 
@@ -61,15 +100,15 @@ __global__ __launch_bounds__(256) void k_net_layer(NetLayerArgs a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[c][i] = Cx<float>{0.f, 0.f};
   if (a.in_same) {
+    Cx<float> v[CIN][3];
+    load_channels<CIN, CIN>(a.in_same, a.g.half, cb, 0, v);
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci) {
-      Cx<float> v[3];
-      load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, v);
 #pragma unroll
       for (int c = 0; c < COUT; ++c) {
         const float2 w = a.w[c * CIN + ci];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) cmac_f(acc[c][i], w, v[i]);
+        for (int i = 0; i < 3; ++i) cmac_f(acc[c][i], w, v[ci][i]);
       }
     }
   }
@@ -89,8 +128,7 @@ __global__ __launch_bounds__(256) void k_net_layer(NetLayerArgs a) {
         }
     }
   }
-#pragma unroll
-  for (int c = 0; c < COUT; ++c) store_spinor<P32>(a.out + (long)c * a.g.half * 3, cb, acc[c]);
+  store_channels<COUT>(a.out, a.g.half, cb, acc);
 }
 
 // Channel mixing on the matrix cores.  For the 64 sites of one wave and one term d (identity or a
@@ -126,8 +164,7 @@ __global__ __launch_bounds__(256) void k_net_layer_mfma(NetLayerArgs a) {
     if (d == 0 ? a.in_same == nullptr : a.in_other == nullptr) continue;  // uniform
     Cx<float> t[CIN][3];
     if (d == 0) {
-#pragma unroll
-      for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+      load_channels<CIN, CIN>(a.in_same, a.g.half, cb, 0, t);
     } else {
       transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
     }
@@ -163,14 +200,15 @@ __global__ __launch_bounds__(256) void k_net_layer_mfma(NetLayerArgs a) {
     __builtin_amdgcn_wave_barrier();
   }
   // C rows 4 kq .. 4 kq + 3 are channels 2 kq and 2 kq + 1, (re, im) each; column 16 j + row.
+  static_assert(COUT % 2 == 0, "matrix-core layers write whole channel pairs");
   const int c0 = 2 * kq;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int n = 16 * j + row;
     const int site = wave_base + n / 3, colour = n % 3;
-    if (site >= a.g.half) continue;
-    if (c0 < COUT) a.out[((long)c0 * a.g.half + site) * 3 + colour] = make_float2(acc[j][0], acc[j][1]);
-    if (c0 + 1 < COUT) a.out[((long)(c0 + 1) * a.g.half + site) * 3 + colour] = make_float2(acc[j][2], acc[j][3]);
+    if (site >= a.g.half || c0 >= COUT) continue;
+    // channels c0, c0 + 1 are one pair of the interleaved layout: one 16-byte store
+    as_global_w<f4v>(a.out + ((long)kq * a.g.half + site) * 6)[colour] = acc[j];
   }
 }
 
@@ -193,15 +231,15 @@ __global__ __launch_bounds__(256) void k_net_wgrad(NetLayerArgs a, const float2*
       const Site s = site_of(cb, a.out_par, a.g);
       Cx<float> t[CIN][3];
       if (d == 0) {
-#pragma unroll
-        for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+        load_channels<CIN, CIN>(a.in_same, a.g.half, cb, 0, t);
       } else {
         transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
       }
+      Cx<float> gvs[G][3];
+      load_channels<COUT, G>(gy, a.g.half, cb, cg * G, gvs);
 #pragma unroll
       for (int c = 0; c < G; ++c) {
-        Cx<float> gv[3];
-        load_spinor<P32>(gy + (long)(cg * G + c) * a.g.half * 3, cb, gv);
+        const Cx<float>* gv = gvs[c];
 #pragma unroll
         for (int ci = 0; ci < CIN; ++ci)
 #pragma unroll
@@ -265,8 +303,7 @@ __global__ __launch_bounds__(kWgradMfmaWG) void k_net_wgrad_mfma(NetLayerArgs a,
       const int cb = live ? cb_raw : a.g.half - 1;
       Cx<float> t[CIN][3];
       if (d == 0) {
-#pragma unroll
-        for (int ci = 0; ci < CIN; ++ci) load_spinor<P32>(a.in_same + (long)ci * a.g.half * 3, cb, t[ci]);
+        load_channels<CIN, CIN>(a.in_same, a.g.half, cb, 0, t);
       } else {
         const Site s = site_of(cb, a.out_par, a.g);
         transported<CIN>(a, s, cb >> 6, cb & 63, d, t);
@@ -276,13 +313,13 @@ __global__ __launch_bounds__(kWgradMfmaWG) void k_net_wgrad_mfma(NetLayerArgs a,
 #pragma unroll
         for (int i = 0; i < 3; ++i)
           xs[wave][ci][3 * lane + i] = live ? make_float2(t[ci][i].re, t[ci][i].im) : make_float2(0.f, 0.f);
+      Cx<float> gvs[COUT][3];
+      load_channels<COUT, COUT>(gy, a.g.half, cb, 0, gvs);
 #pragma unroll
-      for (int c = 0; c < COUT; ++c) {
-        Cx<float> gv[3];
-        load_spinor<P32>(gy + (long)c * a.g.half * 3, cb, gv);
+      for (int c = 0; c < COUT; ++c)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) gs[wave][c][3 * lane + i] = live ? make_float2(gv[i].re, gv[i].im) : make_float2(0.f, 0.f);
-      }
+        for (int i = 0; i < 3; ++i)
+          gs[wave][c][3 * lane + i] = live ? make_float2(gvs[c][i].re, gvs[c][i].im) : make_float2(0.f, 0.f);
       __builtin_amdgcn_wave_barrier();
       // inner step ks covers n = 2 ks + (kq >> 1), part = kq & 1
       const int c = row >> 1, ri = row & 1, part = kq & 1;
