@@ -63,9 +63,13 @@ def cpu_baseline(fat, lng, b, dims, mass, iters_fp64):
     from oracle.cg import cg
     from oracle.dslash import apply_m
 
-    t0 = time.perf_counter()
-    cg(lambda v: apply_m(fat, lng, v, dims, mass), b, tol=1e-10, max_iter=1, max_restarts=0)
-    dt = time.perf_counter() - t0
+    # pin every BLAS / OpenMP pool numpy may use to one thread, so that "cores" is what ran
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        cg(lambda v: apply_m(fat, lng, v, dims, mass), b, tol=1e-10, max_iter=1, max_restarts=0)
+        dt = time.perf_counter() - t0
     per_iter = dt / 3.0   # three operator applications: r = b - A x, one iteration, the true residual
     return {"value": per_iter * iters_fp64, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"one oracle CG iteration on {dims[0]}^3x{dims[3]} ({dt:.1f} s for 3 operator "
