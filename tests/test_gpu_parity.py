@@ -229,16 +229,18 @@ def test_argument_errors(gpu_lib):
     assert st == 1  # STAG_ERR_ARG
 
 
-def test_dslash_full_size_28cubed_96_sampled(gpu_lib):
+@pytest.mark.parametrize("long_su3", [False, True])
+def test_dslash_full_size_28cubed_96_sampled(gpu_lib, long_su3):
     """The paper-shaped lattice 28^3 x 96 in the launch shape the solver uses: sampled sites vs the oracle."""
     dims = (28, 28, 28, 96)
-    print("dslash 28^3x96 sampled", flush=True)
+    print(f"dslash 28^3x96 sampled long_su3={long_su3}", flush=True)
     fat = fat_field(dims, 2001)
     lng = random_su3_field(dims, 2002)
     from paper_1010_4782_amd.stagcg import Lattice
 
     lat = Lattice(dims)
-    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"))
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"),
+                   long_su3=long_su3)
     b = gaussian_source(dims, 2010)[0]
     rng = np.random.default_rng(3)
     half = len(b)
@@ -247,6 +249,32 @@ def test_dslash_full_size_28cubed_96_sampled(gpu_lib):
         out = lat.dslash(torch.from_numpy(b).cuda(), par).cpu().numpy()
         ref = dslash_at_sites(fat, lng, b, dims, par, sample)
         assert rel(out[sample], ref) <= 1e-12
+
+
+def test_dslash_full_size_48cubed_144_eight_rhs_sampled(gpu_lib):
+    """The largest single-GPU workload, 48^3 x 144 with 8 right-hand sides, in the launch shape its
+    benchmark runs (8 right-hand sides per lane, 12-real long links): sampled sites of every RHS vs
+    the oracle, both output parities."""
+    from paper_1010_4782_amd.stagcg import Lattice
+    from stag_inputs import WORKLOADS, workload_links, workload_sources
+
+    dims, nrhs = WORKLOADS[5]["lattices"][0]
+    print(f"dslash {dims} x {nrhs} RHS sampled (input generation takes about a minute)", flush=True)
+    fat, lng = workload_links(5)
+    b = workload_sources(5)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64",), long_su3=True)
+    lat.set_dslash_shape("f64", nrhs, 64, 8)
+    bt = torch.from_numpy(b).cuda()
+    half = b.shape[1]
+    rng = np.random.default_rng(5)
+    sample = np.concatenate([rng.integers(0, half, 96), np.arange(32), np.arange(half - 32, half)])
+    for par in (0, 1):
+        out = lat.dslash(bt, par).cpu().numpy()
+        for r in range(nrhs):
+            ref = dslash_at_sites(fat, lng, b[r], dims, par, sample)
+            assert rel(out[r][sample], ref) <= 1e-12, (par, r)
+    lat.set_dslash_shape("f64", nrhs, 0, 1)
 
 
 def test_dslash_identical_for_every_launch_shape(gpu_lib):
