@@ -183,3 +183,26 @@ def test_net_refuses_when_fp32_links_were_dropped(gpu_lib):
         lat.cg_solve(b, 0.1, tol=1e-10, net=net)
     lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32"))
     net.apply(b)  # usable again once the FP32 links are back
+
+
+def test_net_forward_full_size_24cubed_48(gpu_lib):
+    """The learned-preconditioner workload's lattice and network (24^3 x 48, 4 layers of 8 channels,
+    the 8 -> 8 layers on the matrix cores) against the FP64 oracle on FP32-rounded links and weights."""
+    from paper_1010_4782_amd.stagcg import Lattice, Net
+    from stag_inputs import WORKLOADS, workload_links
+
+    w = WORKLOADS[4]
+    dims = w["lattices"][0][0]
+    print(f"net forward full size {dims} (about half a minute of oracle time)", flush=True)
+    fat, lng = workload_links(4)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32"),
+                   long_su3=True)
+    channels = [1] + [w["channels"]] * (w["layers"] - 1) + [1]
+    net = Net(lat, layers=w["layers"], channels=w["channels"])
+    W32 = [quant.to_f32(x) for x in init_weights(channels, 41, scale=1.0)]
+    net.set_weights(W32)
+    r = gaussian_source(dims, 42, 1)
+    out = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = net_forward(quant.to_f32(folded_fat(fat, dims)), W32, quant.to_f32(r[0]), dims)
+    assert rel(out[0], ref) <= 2e-5
