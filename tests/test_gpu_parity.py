@@ -407,3 +407,29 @@ def test_batch_rejects_mixed_long_link_storage(gpu_lib):
     b = torch.from_numpy(gaussian_source(dims, 125)).cuda()
     with pytest.raises(StagError):
         cg_solve_batch([(lat_a, b, [0.1], None), (lat_b, b, [0.1], None)], tol=1e-10)
+
+
+def test_batched_full_size_uneven_lattices(gpu_lib):
+    """The batched workload at full size: 16^4 x 4 + 24^3x48 x 12 + 32^3x64 x 8 right-hand sides in one
+    batch (mass 0.01, the hardest of its three), mixed precision with the autotuner, 12-real links.
+    Every RHS must report convergence; the first RHS of each lattice is re-checked by the oracle."""
+    from paper_1010_4782_amd.stagcg import Lattice, cg_solve_batch
+    from stag_inputs import WORKLOADS, workload_links, workload_sources
+
+    w = WORKLOADS[3]
+    mass = w["masses"][0]
+    print("batched full size (input generation and oracle checks take about a minute)", flush=True)
+    probs, hosts = [], []
+    for li, (dims, nrhs) in enumerate(w["lattices"]):
+        fat, lng = workload_links(3, li)
+        b = workload_sources(3, li)
+        lat = Lattice(dims)
+        lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"),
+                       long_su3=True)
+        probs.append((lat, torch.from_numpy(b).cuda(), [mass] * nrhs, None))
+        hosts.append((fat, lng, dims, b))
+    xs, infos = cg_solve_batch(probs, tol=w["tol"], prec="f16", autotune=True)
+    assert all(i["converged"] == 1 and i["true_resid"] <= w["tol"] for i in infos)
+    for (fat, lng, dims, b), x in zip(hosts, xs):
+        x0 = x[0].cpu().numpy()
+        assert true_residual(lambda v: apply_m(fat, lng, v, dims, mass), b[0], x0) <= 1.05 * w["tol"]
