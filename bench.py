@@ -185,6 +185,73 @@ def run_learned_preconditioner(a, out_json):
     return 0
 
 
+def run_shard_demo(a):
+    """One GPU's share of a t-decomposed Dslash (the design of a multi-GPU run, exercised on one GPU):
+    P slabs of Lt/P slices, each with its two 3-slice faces copied in from its neighbours; the slab
+    Dslash of every slab must equal the unsplit Dslash bit for bit.  Times the unsplit launch, one slab
+    launch and one face copy (device to device on this GPU), all FP64, with HIP events."""
+    import torch
+
+    from paper_1010_4782_amd.stagcg import Lattice
+    from stag_inputs import WORKLOADS, workload_links, workload_sources
+
+    w = WORKLOADS[a.workload]
+    dims, nrhs = w["lattices"][0]
+    P = a.shard_demo
+    Lt = dims[3]
+    if Lt % P or (Lt // P) % 2:
+        print(f"--shard-demo {P}: Lt = {Lt} must split into P slabs of an even number of slices", file=sys.stderr)
+        return 2
+    lt = Lt // P
+    fat, lng = workload_links(a.workload)
+    b = torch.from_numpy(workload_sources(a.workload)).cuda()
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0, precs=("f64",),
+                   long_su3=not a.no_long_su3)
+    del fat, lng
+    S = lat.half // Lt
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=10):
+        fn()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    par = 1
+    ref = lat.dslash(b, par)
+    ok = True
+    ext = torch.empty((nrhs, (lt + 6) * S, 3), dtype=torch.complex128, device="cuda")
+    for k in range(P):
+        t0 = k * lt
+        lo, hi = ((t0 - 3) % Lt) * S, ((t0 + lt) % Lt) * S
+        ext[:, 3 * S:(lt + 3) * S] = b[:, t0 * S:(t0 + lt) * S]          # own slices
+        ext[:, :3 * S] = b[:, lo:lo + 3 * S]                              # face from slab k-1
+        ext[:, (lt + 3) * S:] = b[:, hi:hi + 3 * S]                        # face from slab k+1
+        out = lat.dslash_slab(ext, par, t0, lt)
+        ok &= bool(torch.equal(out, ref[:, t0 * S:(t0 + lt) * S]))
+    face = b[:, :3 * S].contiguous()
+    recv = torch.empty_like(face)
+    us_full = timed(lambda: lat.dslash(b, par, out=ref))
+    out = torch.empty((nrhs, lt * S, 3), dtype=torch.complex128, device="cuda")
+    us_slab = timed(lambda: lat.dslash_slab(ext, par, 0, lt, out=out))
+    us_face = timed(lambda: recv.copy_(face))
+    face_bytes = face.numel() * 16
+    res = {"metric": "shard demo: slab Dslash on one GPU's share, loopback exchange", "workload": w["name"],
+           "dims": list(dims), "nrhs": nrhs, "slabs": P, "slab_dims": [dims[0], dims[1], dims[2], lt],
+           "loopback_bitwise_equal": ok, "dslash_f64_unsplit_us": us_full, "dslash_f64_slab_us": us_slab,
+           "slab_over_unsplit": us_slab / us_full, "face_bytes_per_direction": face_bytes,
+           "face_copy_device_us": us_face,
+           "face_over_xgmi_link_us_estimate": face_bytes / 153e9 * 1e6,
+           "note": "xGMI time is face bytes / 153 GB/s (one link), an estimate: no second GPU here"}
+    print(json.dumps(res), flush=True)
+    return 0 if ok else 1
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +272,10 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=5, help="workload 4: training epochs")
     ap.add_argument("--lr", type=float, default=2e-3, help="workload 4: Adam step size")
     ap.add_argument("--loss", default="residual", choices=["residual", "solution"], help="workload 4: training loss")
+    ap.add_argument("--shard-demo", type=int, default=0, metavar="P",
+                    help="instead of the solve: split the workload's first lattice into P time slabs (one per GPU "
+                         "of a multi-GPU run), exchange the 3-slice faces on this one GPU, apply the slab Dslash, "
+                         "check the assembled result against the unsplit one and time both")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU runs are not supported.",
@@ -213,6 +284,8 @@ def main(argv=None):
 
     if a.workload == 4:
         return run_learned_preconditioner(a, None)
+    if a.shard_demo:
+        return run_shard_demo(a)
 
     import numpy as np
     import torch

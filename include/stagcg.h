@@ -160,6 +160,19 @@ stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng
 stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, void* out,
                         int32_t nrhs, int32_t prec, void* stream);
 
+/* The Dslash of one time slab, for domain decomposition along t (the paper's multi-GPU split,
+ * Sec. 4; one GPU per slab, here exercised on one GPU): out = D_{p,1-p} in on the slices
+ * [t0, t0 + lt) only, the input read from an extended field that holds the 3 slices before t0, the lt
+ * slices, and the 3 slices after (indices mod Lt) - what a GPU owning the slab holds once its two
+ * 3-slice faces (the Naik term's depth) have arrived from its neighbours.  A face is contiguous in
+ * the even-odd layout (slices are the slowest index), so the exchange is one copy per face.
+ * t0, lt: even, lt >= 2, t0 + lt <= Lt.  in_ext: device complex128 [nrhs][(lt + 6) * S][3] on parity
+ * 1-p, S = Lx Ly Lz / 2 sites per slice and parity; out: [nrhs][lt * S][3] on parity p; not
+ * overlapping.  The links are the lattice's own (loaded for the whole lattice); prec as stag_dslash.
+ * The result equals the rows [t0 S, (t0 + lt) S) of stag_dslash bit for bit. */
+stag_status stag_dslash_slab(stag_lattice_t lat, int32_t out_parity, int32_t t0, int32_t lt, const void* in_ext,
+                             void* out, int32_t nrhs, int32_t prec, void* stream);
+
 /* out = M in = 4 m^2 in - D_eo D_oe in on even sites (Eq. (3)), FP64.
  * mass: host double[nrhs]; in, out: device complex128 [nrhs][V/2][3], not overlapping. */
 stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,

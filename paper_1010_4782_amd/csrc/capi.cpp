@@ -153,7 +153,7 @@ stag_status ring_release(Ctl& c, const RingEntry& e, hipStream_t st) {
 
 // Set up a single-problem batch whose table, scalars and partials live in a ring entry.
 stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* const* vec_override, hipStream_t st,
-                         BatchHost& bh, RingEntry& e) {
+                         BatchHost& bh, RingEntry& e, const Geo* geo_override = nullptr) {
   const int pstride = ceil_div(L->g.half, kWave);
   const size_t off_scal = (sizeof(ProbDev) + 255) & ~size_t(255);
   const size_t off_part = off_scal + ((sizeof(Scal) * nrhs + 255) & ~size_t(255));
@@ -161,6 +161,7 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
   stag_status s = ring_acquire(L->ctl, need, e);
   if (s != STAG_OK) return s;
   ProbDev pd = prob_dev(L, nrhs, 0);
+  if (geo_override) pd.g = *geo_override;
   for (int v = 0; v < kNumVec; ++v) pd.vec[v] = L->vec[v].ptr;
   for (int v = 0; v < kNumVec; ++v)
     if (vec_override[v]) pd.vec[v] = vec_override[v];
@@ -172,13 +173,13 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
     sc[r] = z;
   }
   STAG_HIP_TRY(hipMemcpyAsync(e.dev, e.host, off_part, hipMemcpyHostToDevice, st));
-  bh.probs.assign(1, HostProb{L->g.half, nrhs, 0});
+  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0});
   bh.d_probs = reinterpret_cast<const ProbDev*>(e.dev);
   bh.d_scal = reinterpret_cast<Scal*>(e.dev + off_scal);
   bh.d_partial = reinterpret_cast<double*>(e.dev + off_part);
   bh.pstride = pstride;
   bh.nslots = nrhs;
-  bh.max_half = L->g.half;
+  bh.max_half = pd.g.half;
   bh.long12 = L->g.long12 != 0;
   return STAG_OK;
 }
@@ -338,6 +339,59 @@ stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, 
   const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec));
   STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
   if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, nsites, st));
+  return ring_release(lat->ctl, e, st);
+  STAG_GUARD_END
+}
+
+stag_status stag_dslash_slab(stag_lattice_t lat, int32_t out_parity, int32_t t0, int32_t lt, const void* in_ext,
+                             void* out, int32_t nrhs, int32_t prec, void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  const int Lt = lat->dims[3];
+  if (out_parity != 0 && out_parity != 1) return arg_error("out_parity must be 0 or 1");
+  if (t0 < 0 || t0 % 2 || lt < 2 || lt % 2 || t0 + lt > Lt)
+    return arg_error("the slab [t0, t0 + lt) must lie in [0, Lt) with t0 and lt even, lt >= 2");
+  if (!in_ext || !out) return arg_error("in_ext and out must not be NULL");
+  if (nrhs < 1) return arg_error("nrhs must be >= 1");
+  if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
+  if (!(lat->built & STAG_PREC_BIT(prec))) return arg_error("the requested precision was not packed by load_links");
+  const long slice = lat->g.stride[3];  // sites of one parity in one time slice
+  const long in_sites = slice * (lt + 6), out_sites = slice * lt;
+  {
+    const char* a = static_cast<const char*>(in_ext);
+    const char* b = static_cast<const char*>(out);
+    if (a < b + (size_t)out_sites * 48 * nrhs && b < a + (size_t)in_sites * 48 * nrhs)
+      return arg_error("in_ext and out must not overlap");
+  }
+  Geo gs = lat->g;
+  gs.L[3] = lt;
+  gs.half = (int)out_sites;
+  gs.in_half = (int)in_sites;
+  gs.h1[3] = 1;
+  gs.h3[3] = 3;
+  gs.t0 = t0;
+  gs.t_open = 1;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* ov[kNumVec] = {};
+  const size_t vb = spinor_bytes(prec);
+  if (prec == STAG_F64) {
+    ov[V_D] = const_cast<char*>(static_cast<const char*>(in_ext)) + 3 * slice * vb;  // first interior slice
+    ov[V_T] = out;
+  } else {
+    STAG_HIP_TRY(lat->io_lo[0].ensure(vb * in_sites * nrhs));
+    STAG_HIP_TRY(lat->io_lo[1].ensure(vb * out_sites * nrhs));
+    STAG_HIP_TRY(launch_convert_from_f64(prec, in_ext, lat->io_lo[0].ptr, in_sites * nrhs, st));
+    ov[V_D] = static_cast<char*>(lat->io_lo[0].ptr) + 3 * slice * vb;
+    ov[V_T] = lat->io_lo[1].ptr;
+  }
+  BatchHost bh;
+  RingEntry e;
+  s = single_batch(lat, nrhs, nullptr, ov, st, bh, e, &gs);
+  if (s != STAG_OK) return s;
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec));
+  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
+  if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, out_sites * nrhs, st));
   return ring_release(lat->ctl, e, st);
   STAG_GUARD_END
 }

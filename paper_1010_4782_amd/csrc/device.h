@@ -369,6 +369,7 @@ __device__ __forceinline__ int neighbour(const Site& s, const Geo& g, int mu, in
   }
   int c = mu == 1 ? s.y : (mu == 2 ? s.z : s.t);
   int cn = fwd ? wrap_fwd(c, h, g.L[mu]) : wrap_bwd(c, h, g.L[mu]);
+  if (mu == 3) cn = g.t_open ? (fwd ? c + h : c - h) : cn;  // a slab reads its ghost slices (a select)
   return s.cb + (cn - c) * g.stride[mu];
 }
 
@@ -380,8 +381,10 @@ __device__ __forceinline__ int long_sign(const Site& s, const Geo& g, int mu, bo
   if (mu == 3) {
     // floor((start + 3) / L_t) for 0 <= start < L_t, L_t >= 2, is (start+3 >= L_t) + (start+3 >= 2 L_t):
     // compares instead of a division or a branch keep the unrolled link loop straight-line code.
-    const int start = fwd ? s.t : wrap_bwd(s.t, g.h3[3], g.L[3]);
-    const int wraps = (start + 3 >= g.L[3]) ^ (start + 3 >= 2 * g.L[3]);
+    // The time coordinate and extent are the whole lattice's (a slab adds its offset t0).
+    const int tg = s.t + g.t0, Lg = g.lt_glob;
+    const int start = fwd ? tg : wrap_bwd(tg, g.h3g, Lg);
+    const int wraps = (start + 3 >= Lg) ^ (start + 3 >= 2 * Lg);
     neg ^= wraps & g.antiper;
   }
   return neg ? -1 : 1;

@@ -60,11 +60,13 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
   const bool live = cb_raw < g.half;
   const int cb = live ? cb_raw : g.half - 1;  // dead lanes read a valid site and store nothing
   const Site s = site_of(cb, out_par, g);
-  const long blk = cb >> 6;
-  const int lane = cb & 63;
+  const long gcb = cb + (long)g.t0 * g.stride[3];  // the site's index in the whole lattice: packed links
+  const long blk = gcb >> 6;
+  const int lane = (int)(gcb & 63);
 
   const long rstride = (long)g.half * spinor_bytes(P);
-  const char* in = reinterpret_cast<const char*>(pd->vec[in_id]) + (long)r0 * rstride;
+  const long rstride_in = (long)g.in_half * spinor_bytes(P);
+  const char* in = reinterpret_cast<const char*>(pd->vec[in_id]) + (long)r0 * rstride_in;
   const char* lbase = reinterpret_cast<const char*>(pd->links[P][out_par]);
   float sc_fat = 1.f, sc_long = 1.f;
   if (P == P16) {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
       for (int r = 0; r < R; ++r) {
         if (!on[r]) continue;
         Cx<T> v[3];
-        load_spinor<P>(in + r * rstride, nb, v);
+        load_spinor<P>(in + r * rstride_in, nb, v);
         matvec_acc(u, v, acc[r]);
       }
     }

@@ -27,6 +27,11 @@ Geo make_geo(const int dims[4]) {
   g.stride[1] = g.Xh;
   g.stride[2] = g.Xh * dims[1];
   g.stride[3] = g.Xh * dims[1] * dims[2];
+  g.t0 = 0;
+  g.lt_glob = dims[3];
+  g.h3g = 3 % dims[3];
+  g.t_open = 0;
+  g.in_half = g.half;
   return g;
 }
 

@@ -45,6 +45,15 @@ struct Geo {
   int stride[4];   // cb distance of one step in y, z, t (stride[0] unused: x is handled by parity)
   int h1[4];       // 1 mod L_mu
   int h3[4];       // 3 mod L_mu
+  // A time slab [t0, t0 + L[3]) of a lattice with lt_glob slices (domain decomposition along t):
+  // t_open = 1 stops the time neighbours from wrapping; they are read from 3 ghost slices on each
+  // side of the input field, which then holds in_half = (L[3] + 6) * stride[3] sites per RHS.
+  // A whole lattice has t0 = 0, lt_glob = L[3], t_open = 0, in_half = half.
+  int t0;
+  int lt_glob;
+  int h3g;         // 3 mod lt_glob
+  int t_open;
+  int in_half;
 };
 
 // Per right-hand-side solver state ("slot"), resident on the device.

@@ -129,6 +129,23 @@ class Lattice:
                                 _stream(stream)), "stag_dslash")
         return out
 
+    def dslash_slab(self, x_ext: torch.Tensor, out_parity: int, t0: int, lt: int, prec: str = "f64", out=None,
+                    stream=None) -> torch.Tensor:
+        """D on the time slab [t0, t0 + lt) from an extended input [nrhs][(lt + 6) S][3] (3 ghost slices
+        on each side, S sites per slice and parity); returns [nrhs][lt S][3]."""
+        S = self.half // self.dims[3]
+        if x_ext.dim() == 2:
+            x_ext = x_ext.unsqueeze(0)
+        if x_ext.dtype != torch.complex128 or not x_ext.is_cuda or not x_ext.is_contiguous():
+            raise ValueError("x_ext must be a contiguous complex128 CUDA tensor")
+        if x_ext.shape[1:] != (int((lt + 6) * S), 3):
+            raise ValueError(f"x_ext has shape {tuple(x_ext.shape)}, expected [nrhs, {(lt + 6) * S}, 3]")
+        nrhs = x_ext.shape[0]
+        out = torch.empty((nrhs, lt * S, 3), dtype=torch.complex128, device=x_ext.device) if out is None else out
+        check(lib().stag_dslash_slab(self._h, int(out_parity), int(t0), int(lt), x_ext.data_ptr(), out.data_ptr(),
+                                     nrhs, PREC[prec], _stream(stream)), "stag_dslash_slab")
+        return out
+
     def apply_m(self, x: torch.Tensor, mass, out=None, stream=None) -> torch.Tensor:
         nrhs = self._vec(x, "in")
         masses = [float(mass)] * nrhs if not isinstance(mass, (list, tuple)) else [float(m) for m in mass]
