@@ -192,6 +192,27 @@ def test_cg_edge_cases(gpu_lib):
         lat.cg_solve(bt[:1].contiguous(), 0.01, max_iter=3, max_restarts=0)
 
 
+def test_cg_degenerate_cases(gpu_lib):
+    """Massless operator (M = D_oe^dag D_oe, positive semi-definite), a non-finite source, and a zero
+    source in mixed precision."""
+    from paper_1010_4782_amd._lib import STAG_ERR_NAN
+
+    print("cg degenerate cases", flush=True)
+    dims = (4, 4, 4, 4)
+    lat, fat, lng = make(dims, seed=71, precs=("f64", "f16"))
+    b = gaussian_source(dims, 72, 1)
+    x, info = lat.cg_solve(torch.from_numpy(b).cuda(), 0.0, tol=1e-10)
+    assert info[0]["converged"] == 1
+    assert true_residual(lambda v: apply_m(fat, lng, v, dims, 0.0), b[0], x[0].cpu().numpy()) <= 1.05e-10
+    bn = b.copy()
+    bn[0, 5, 1] = np.nan
+    xn, infon = lat.cg_solve(torch.from_numpy(bn).cuda(), 0.1, raise_on_fail=False)
+    assert infon[0]["status"] == STAG_ERR_NAN and infon[0]["converged"] == 0
+    z = torch.zeros_like(torch.from_numpy(b)).cuda()
+    xz, infoz = lat.cg_solve(z, 0.1, prec="f16")
+    assert infoz[0]["iters"] == 0 and not xz.abs().max().item()
+
+
 def test_solves_are_deterministic(gpu_lib):
     dims = (6, 6, 6, 6)
     print("determinism", flush=True)
