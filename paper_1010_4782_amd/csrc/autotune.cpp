@@ -1,5 +1,5 @@
-// Autotuner for the Dslash launch shape: workgroup size (sites per workgroup) and
-// right-hand sides per lane.  Candidates are timed with HIP events on the caller's
+// Autotuner for the Dslash launch shape: workgroup size (sites per workgroup),
+// right-hand sides per lane and LDS staging of the x/y neighbour window.  Candidates are timed with HIP events on the caller's
 // stream on the real buffers of the call; winners are kept per key
 // (lattice shapes, right-hand sides, storage precision) in memory and can be saved
 // to / loaded from a small JSON file.
@@ -36,10 +36,15 @@ int rhs_divisor(const BatchHost& bh) {
   return r;
 }
 
-DslashShape heuristic(const BatchHost& bh) {
+// Untuned default, from sweeps on 28^3x96 (1-8 RHS, every precision): one RHS per lane runs best in
+// 64-site workgroups; with several RHS, 4 per lane in 256-site workgroups with the LDS window staged is
+// the fastest or within 4% of it.
+DslashShape heuristic(const BatchHost& bh, int prec) {
   DslashShape s;
-  s.wg = 256;
-  s.r = rhs_divisor(bh);
+  s.r = std::min(rhs_divisor(bh), 4);
+  s.wg = s.r == 1 ? 64 : 256;
+  s.lds = s.r > 1 ? 1 : 0;
+  if (!dslash_shape_valid(bh, prec, s)) s.lds = 0;
   return s;
 }
 
@@ -49,15 +54,16 @@ std::string tune_key(const BatchHost& bh, const std::vector<const stag_lattice_s
   return key_of(bh, lats, prec);
 }
 
-DslashShape lookup_shape(const BatchHost& bh, const std::string& key) {
+DslashShape lookup_shape(const BatchHost& bh, const std::string& key, int prec) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(key);
   if (it != g_table.end()) {
     DslashShape s = it->second;
     s.r = std::min(s.r, rhs_divisor(bh));
+    if (!dslash_shape_valid(bh, prec, s)) s.lds = 0;  // a loaded table entry whose window does not fit
     return s;
   }
-  return heuristic(bh);
+  return heuristic(bh, prec);
 }
 
 void pin_shape(const std::string& key, const DslashShape& s) {
@@ -89,22 +95,26 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
   float best_us = 1e30f;
   const int reps = 5;
   for (int wg : {64, 128, 256}) {
-    for (int r = 1; r <= rmax; r *= 2) {
-      for (int w = 0; w < 2 && e == hipSuccess; ++w)
-        e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, wg, r, st);
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int i = 0; i < reps && e == hipSuccess; ++i)
-        e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, wg, r, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      const float us = 1e3f * ms / reps;
-      if (all) all->push_back({DslashShape{wg, r}, us});
-      if (us < best_us) {
-        best_us = us;
-        best = DslashShape{wg, r};
+    for (int r = 1; r <= rmax && e == hipSuccess; r *= 2) {
+      for (int lds = 0; lds < 2; ++lds) {
+        const DslashShape sh{wg, r, lds};
+        if (!dslash_shape_valid(bh, prec, sh)) continue;
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+          e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, sh, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int i = 0; i < reps && e == hipSuccess; ++i)
+          e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, sh, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        const float us = 1e3f * ms / reps;
+        if (all) all->push_back({sh, us});
+        if (us < best_us) {
+          best_us = us;
+          best = sh;
+        }
       }
     }
   }
@@ -124,14 +134,14 @@ bool save_table(const char* path) {
   f << "{\n";
   size_t i = 0;
   for (const auto& kv : g_table) {
-    f << "  \"" << kv.first << "\": [" << kv.second.wg << ", " << kv.second.r << "]"
+    f << "  \"" << kv.first << "\": [" << kv.second.wg << ", " << kv.second.r << ", " << kv.second.lds << "]"
       << (++i < g_table.size() ? ",\n" : "\n");
   }
   f << "}\n";
   return (bool)f;
 }
 
-// Reads the format save_table writes: one "key": [wg, r] pair per line.
+// Reads the format save_table writes: one "key": [wg, r, lds] entry per line (lds may be absent: 0).
 bool load_table(const char* path, int* n_loaded) {
   std::ifstream f(path);
   if (!f) return false;
@@ -144,10 +154,12 @@ bool load_table(const char* path, int* n_loaded) {
     const size_t q1 = line.find('"', q0 + 1);
     const size_t b0 = line.find('[', q1);
     if (q1 == std::string::npos || b0 == std::string::npos) return false;
-    int wg = 0, r = 0;
-    if (std::sscanf(line.c_str() + b0, "[%d , %d]", &wg, &r) != 2) return false;
-    if ((wg != 64 && wg != 128 && wg != 256) || (r != 1 && r != 2 && r != 4 && r != 8)) return false;
-    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r};
+    int wg = 0, r = 0, lds = 0;
+    const int got = std::sscanf(line.c_str() + b0, "[%d , %d , %d]", &wg, &r, &lds);
+    if (got < 2) return false;
+    if ((wg != 64 && wg != 128 && wg != 256) || (r != 1 && r != 2 && r != 4 && r != 8) || (lds != 0 && lds != 1))
+      return false;
+    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r, lds};
     ++n;
   }
   std::lock_guard<std::mutex> lk(g_mu);

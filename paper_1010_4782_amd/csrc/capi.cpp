@@ -173,7 +173,7 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
     sc[r] = z;
   }
   STAG_HIP_TRY(hipMemcpyAsync(e.dev, e.host, off_part, hipMemcpyHostToDevice, st));
-  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0});
+  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh});
   bh.d_probs = reinterpret_cast<const ProbDev*>(e.dev);
   bh.d_scal = reinterpret_cast<Scal*>(e.dev + off_scal);
   bh.d_partial = reinterpret_cast<double*>(e.dev + off_part);
@@ -336,8 +336,8 @@ stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, 
   RingEntry e;
   s = single_batch(lat, nrhs, nullptr, ov, st, bh, e);
   if (s != STAG_OK) return s;
-  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec));
-  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec), prec);
+  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh, st));
   if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, nsites, st));
   return ring_release(lat->ctl, e, st);
   STAG_GUARD_END
@@ -389,8 +389,8 @@ stag_status stag_dslash_slab(stag_lattice_t lat, int32_t out_parity, int32_t t0,
   RingEntry e;
   s = single_batch(lat, nrhs, nullptr, ov, st, bh, e, &gs);
   if (s != STAG_OK) return s;
-  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec));
-  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh.wg, sh.r, st));
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, prec), prec);
+  STAG_HIP_TRY(launch_dslash(bh, prec, EPI_PLAIN, out_parity, V_D, V_T, 0, 0, 3, sh, st));
   if (prec != STAG_F64) STAG_HIP_TRY(launch_convert_to_f64(prec, lat->io_lo[1].ptr, out, out_sites * nrhs, st));
   return ring_release(lat->ctl, e, st);
   STAG_GUARD_END
@@ -415,9 +415,9 @@ stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in,
   RingEntry e;
   s = single_batch(lat, nrhs, mass, ov, st, bh, e);
   if (s != STAG_OK) return s;
-  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, P64));
-  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh.wg, sh.r, st));
-  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh.wg, sh.r, st));
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, P64), P64);
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh, st));
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh, st));
   return ring_release(lat->ctl, e, st);
   STAG_GUARD_END
 }
@@ -463,13 +463,13 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
   if (s != STAG_OK) return s;
   float best_us = 0.f;
   for (const auto& t : timed)
-    if (t.first.wg == b.wg && t.first.r == b.r) best_us = t.second;
-  if (best) *best = stag_shape{b.wg, b.r, best_us};
+    if (t.first.wg == b.wg && t.first.r == b.r && t.first.lds == b.lds) best_us = t.second;
+  if (best) *best = stag_shape{b.wg, b.r, b.lds, best_us};
   if (all) {
     int n = 0;
     for (const auto& t : timed) {
       if (n >= max_all) break;
-      all[n++] = stag_shape{t.first.wg, t.first.r, t.second};
+      all[n++] = stag_shape{t.first.wg, t.first.r, t.first.lds, t.second};
     }
     if (n_all) *n_all = n;
   }
@@ -477,7 +477,8 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
   STAG_GUARD_END
 }
 
-stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane) {
+stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane,
+                                  int32_t lds_stage) {
   STAG_GUARD_BEGIN
   if (!lat) return arg_error("lattice is NULL");
   if (nrhs < 1) return arg_error("nrhs must be >= 1");
@@ -486,10 +487,14 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   if (wg != 0 && rhs_per_lane != 1 && rhs_per_lane != 2 && rhs_per_lane != 4 && rhs_per_lane != 8)
     return arg_error("rhs_per_lane must be 1, 2, 4 or 8");
   if (wg != 0 && nrhs % rhs_per_lane) return arg_error("rhs_per_lane must divide nrhs");
+  if (lds_stage != 0 && lds_stage != 1) return arg_error("lds_stage must be 0 or 1");
   BatchHost bh;
-  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0});
+  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0, lat->g.Xh});
   bh.long12 = lat->g.long12 != 0;
-  pin_shape(single_key(bh, lat, prec), DslashShape{wg, rhs_per_lane});
+  const DslashShape sh{wg, rhs_per_lane, lds_stage};
+  if (wg != 0 && !dslash_shape_valid(bh, prec, sh))
+    return arg_error("the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
+  pin_shape(single_key(bh, lat, prec), sh);
   return STAG_OK;
   STAG_GUARD_END
 }

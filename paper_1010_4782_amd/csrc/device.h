@@ -91,6 +91,25 @@ template <> __device__ __forceinline__ void load_spinor<P16>(const void* base, l
   v[2] = unpack_h2(w.z, sc);
 }
 
+// The same reads from a colour-vector array staged in LDS (index s relative to the staged window).
+template <int P> __device__ __forceinline__ void load_spinor_lds(const char* base, int s, Cx<typename RealOf<P>::T> v[3]) {
+  if constexpr (P == P64) {
+    const d2v* p = reinterpret_cast<const d2v*>(base) + 3 * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = Cx<double>{p[c].x, p[c].y};
+  } else if constexpr (P == P32) {
+    const f2v* p = reinterpret_cast<const f2v*>(base) + 3 * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = Cx<float>{p[c].x, p[c].y};
+  } else {
+    const u4v w = reinterpret_cast<const u4v*>(base)[s];
+    const float sc = __uint_as_float(w.w);
+    v[0] = unpack_h2(w.x, sc);
+    v[1] = unpack_h2(w.y, sc);
+    v[2] = unpack_h2(w.z, sc);
+  }
+}
+
 // Store and return the stored (rounded) value in v.
 template <int P> __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]);
 

@@ -8,6 +8,8 @@
 // link stream is the compulsory traffic (16 x 144 B per site in FP64) and is
 // read with non-temporal loads; neighbour colour vectors come through L1/L2,
 // which the XCD-aware block order keeps local.
+#include <algorithm>
+
 #include "device.h"
 #include "launch.h"
 
@@ -32,9 +34,18 @@ __device__ __forceinline__ void dslash_issue(int k, const Site& s, const Geo& g,
 // and these distances are 6% (f16), 8% (f32) and 9% (f64) faster.
 template <int P> constexpr int dslash_pf() { return P == P16 ? 12 : (P == P32 ? 8 : 6); }
 
-template <int P, int R, int EPI, bool C12, int PF>
+// LDS staging (LDS = true): before the link loop a workgroup copies into LDS the colour vectors of
+// the window [c0 - 3 Xh, c0 + wg + 3 Xh) of its first site c0 (for each of its RHS); the x and y
+// neighbours of its sites that fall in the window (all but the y neighbours that wrap around the
+// lattice) are then read from LDS instead of through L1/L2.  Same arithmetic, same result.
+extern __shared__ __align__(16) char dslash_window[];
+
+__host__ __device__ constexpr int window_margin(int xh) { return 3 * xh; }
+
+template <int P, int R, int EPI, bool C12, int PF, bool LDS>
 __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
                                                    int b_id, int gate) {
+  static_assert(!(LDS && PF > 0), "the staged path uses the plain link loop");
   using T = typename RealOf<P>::T;
   __shared__ double lds[R * 4];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -81,6 +92,27 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] = Cx<T>{T(0), T(0)};
 
+  // LDS window: sites [w0, w0 + wn) of every active RHS, 8-byte units, loaded by the whole workgroup
+  const int w0 = tile * (int)blockDim.x - window_margin(g.Xh);
+  const int wn = (int)blockDim.x + 2 * window_margin(g.Xh);
+  constexpr int SB = spinor_bytes(P);
+  if constexpr (LDS) {
+    const int units = wn * SB / 8;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!on[r]) continue;  // uniform over the workgroup
+      // window sites outside [0, in_half) are never read back: every neighbour index is in range
+      const char* src = in + r * rstride_in;
+      char* dst = dslash_window + r * wn * SB;
+      for (int u = threadIdx.x; u < units; u += blockDim.x) {
+        const int site = w0 + (u * 8) / SB;
+        if (site >= 0 && site < g.in_half)
+          *reinterpret_cast<u2v*>(dst + u * 8) = *as_global<u2v>(src + (long)w0 * SB + (long)u * 8);
+      }
+    }
+    __syncthreads();
+  }
+
   if constexpr (PF > 0) {
     // Software pipeline over the 16 links: the loads of link k + PF are issued while link k is
     // multiplied.  An empty volatile asm that takes the accumulators closes each stage: the
@@ -117,11 +149,15 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
       Cx<T> u[9];
       load_link<P, C12>(lbase, blk, 4 * mu + j, lane, j < 2 ? sc_fat : sc_long, u);
       if (C12 && j >= 2) rebuild_row3(u, (T)(long_sign(s, g, mu, j == 2) * g.cn_inv));
+      const bool from_lds = LDS && mu < 2 && (unsigned)(nb - w0) < (unsigned)wn;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!on[r]) continue;
         Cx<T> v[3];
-        load_spinor<P>(in + r * rstride_in, nb, v);
+        if (from_lds)
+          load_spinor_lds<P>(dslash_window + r * wn * SB, nb - w0, v);
+        else
+          load_spinor<P>(in + r * rstride_in, nb, v);
         matvec_acc(u, v, acc[r]);
       }
     }
@@ -192,25 +228,28 @@ Batch make_batch(const BatchHost& bh, int wg, int r) {
   return B;
 }
 
-template <int P, int R, bool C12>
+template <int P, int R, bool C12, bool LDS>
 static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
-                           int gate, int wg, hipStream_t st) {
-  constexpr int PF = R == 1 ? dslash_pf<P>() : 0;
-  constexpr int PF64 = R == 1 ? dslash_pf<P64>() : 0;
+                           int gate, int wg, size_t lds_bytes, hipStream_t st) {
+  constexpr int PF = (R == 1 && !LDS) ? dslash_pf<P>() : 0;
+  constexpr int PF64 = (R == 1 && !LDS) ? dslash_pf<P64>() : 0;
   switch (epi) {
     case EPI_PLAIN:
-      k_dslash<P, R, EPI_PLAIN, C12, PF><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_PLAIN, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
       break;
     case EPI_XPAY_DOT:
-      k_dslash<P, R, EPI_XPAY_DOT, C12, PF><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_XPAY_DOT, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
+                                                                            gate);
       break;
     case EPI_RESID:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_RESID, C12, PF64><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_RESID, C12, PF64, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
+                                                                             gate);
       break;
     case EPI_XPAY:
       if (P != P64) return hipErrorInvalidValue;
-      k_dslash<P64, R, EPI_XPAY, C12, PF64><<<nblk, wg, 0, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P64, R, EPI_XPAY, C12, PF64, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
+                                                                            gate);
       break;
     default:
       return hipErrorInvalidValue;
@@ -218,37 +257,55 @@ static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int i
   return hipGetLastError();
 }
 
-template <int P, bool C12>
+template <int P, bool C12, bool LDS>
 static hipError_t dslash_p(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
-                           int gate, int wg, int r, hipStream_t st) {
+                           int gate, int wg, int r, size_t lds_bytes, hipStream_t st) {
   switch (r) {
-    case 1: return dslash_r<P, 1, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 2: return dslash_r<P, 2, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 4: return dslash_r<P, 4, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
-    case 8: return dslash_r<P, 8, C12>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, st);
+    case 1: return dslash_r<P, 1, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
+    case 2: return dslash_r<P, 2, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
+    case 4: return dslash_r<P, 4, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
+    case 8: return dslash_r<P, 8, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <int P>
+static hipError_t dslash_pc(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
+                            int gate, const DslashShape& sh, bool c12, size_t lds_bytes, hipStream_t st) {
+  if (c12)
+    return sh.lds ? dslash_p<P, true, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, lds_bytes, st)
+                  : dslash_p<P, true, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, 0, st);
+  return sh.lds ? dslash_p<P, false, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, lds_bytes, st)
+                : dslash_p<P, false, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, 0, st);
+}
+
+// The LDS window holds wg + 6 Xh sites (of the widest lattice of the batch) per RHS of a lane.
+size_t dslash_lds_bytes(const BatchHost& bh, int prec, const DslashShape& sh) {
+  if (!sh.lds) return 0;
+  int xh = 0;
+  for (const auto& p : bh.probs) xh = std::max(xh, p.xh);
+  return (size_t)sh.r * (sh.wg + 2 * window_margin(xh)) * spinor_bytes(prec);
+}
+
+bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh) {
+  if (sh.wg != 64 && sh.wg != 128 && sh.wg != 256) return false;
+  if (sh.r != 1 && sh.r != 2 && sh.r != 4 && sh.r != 8) return false;
+  return dslash_lds_bytes(bh, prec, sh) <= kMaxDslashLds;
+}
+
 hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
-                         int b_id, int gate, int wg, int r, hipStream_t st) {
-  if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
-  const Batch B = make_batch(bh, wg, r);
+                         int b_id, int gate, const DslashShape& sh, hipStream_t st) {
+  if (!dslash_shape_valid(bh, prec, sh)) return hipErrorInvalidValue;
+  const Batch B = make_batch(bh, sh.wg, sh.r);
   const int nblk = B.block_start[B.nprob];
   if (nblk == 0) return hipSuccess;
   const bool c12 = bh.long12;
+  const size_t lds = dslash_lds_bytes(bh, prec, sh);
   switch (prec) {
-    case P64:
-      return c12 ? dslash_p<P64, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
-                 : dslash_p<P64, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    case P32:
-      return c12 ? dslash_p<P32, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
-                 : dslash_p<P32, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    case P16:
-      return c12 ? dslash_p<P16, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st)
-                 : dslash_p<P16, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, r, st);
-    default:
-      return hipErrorInvalidValue;
+    case P64: return dslash_pc<P64>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh, c12, lds, st);
+    case P32: return dslash_pc<P32>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh, c12, lds, st);
+    case P16: return dslash_pc<P16>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh, c12, lds, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -19,7 +19,10 @@ struct HostProb {
   int half;
   int nrhs;
   int slot0;
+  int xh = 0;  // Lx / 2 (width of the LDS window margin of a staged Dslash)
 };
+
+constexpr size_t kMaxDslashLds = 64 * 1024;  // LDS a staged Dslash workgroup may use
 
 struct BatchHost {
   std::vector<HostProb> probs;
@@ -35,8 +38,18 @@ struct BatchHost {
 // Block map for a launch with `wg` sites per workgroup and `r` right-hand sides per lane.
 Batch make_batch(const BatchHost& bh, int wg, int r);
 
+// Launch shape of a Dslash: sites per workgroup, right-hand sides per lane, LDS staging.
+struct DslashShape {
+  int wg = 256;
+  int r = 1;
+  int lds = 0;  // 1: stage the x and y neighbour colour vectors of a workgroup's sites in LDS
+};
+
+// Bytes of LDS a staged launch of this shape needs (0 if unstaged), and whether it fits.
+size_t dslash_lds_bytes(const BatchHost& bh, int prec, const DslashShape& sh);
+bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh);
 hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
-                         int b_id, int gate, int wg, int r, hipStream_t st);
+                         int b_id, int gate, const DslashShape& sh, hipStream_t st);
 
 // Vector stages of the solvers (every one is one launch over all slots of the batch).
 hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st);

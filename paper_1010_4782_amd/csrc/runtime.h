@@ -29,10 +29,6 @@ struct HostBuf {
 };
 
 // Launch shape of the Dslash for one (precision, nrhs, lattice) combination.
-struct DslashShape {
-  int wg = 256;
-  int r = 1;
-};
 
 struct Lattice;
 
@@ -78,7 +74,7 @@ ProbDev prob_dev(const stag_lattice_s* lat, int nrhs, int slot0);
 
 // Autotuner (autotune.cpp): launch shapes keyed by (precision, lattice shapes, right-hand sides).
 std::string tune_key(const BatchHost& bh, const std::vector<const stag_lattice_s*>& lats, int prec);
-DslashShape lookup_shape(const BatchHost& bh, const std::string& key);
+DslashShape lookup_shape(const BatchHost& bh, const std::string& key, int prec);
 void pin_shape(const std::string& key, const DslashShape& s);
 bool has_shape(const std::string& key);
 hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hipStream_t st, DslashShape* best,

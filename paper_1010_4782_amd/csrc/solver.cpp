@@ -86,8 +86,8 @@ hipError_t record(Run& R, bool on) {
 // V_R = b - M x (FP64), aux = ||V_R|| / ||b||, delta = |V_R|^2, for slots passing `gate`.
 hipError_t true_residual(Run& R, int gate) {
   const DslashShape s64 = R.shape64;
-  hipError_t e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_X, V_TMPO, 0, 0, gate, s64.wg, s64.r, R.st);
-  if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_RESID, 0, V_TMPO, V_R, V_X, V_B, gate, s64.wg, s64.r, R.st);
+  hipError_t e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_X, V_TMPO, 0, 0, gate, s64, R.st);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_RESID, 0, V_TMPO, V_R, V_X, V_B, gate, s64, R.st);
   if (e == hipSuccess) e = launch_finalize(R.bh, FIN_TRUE, 1, gate, s64.wg, nullptr, 0, R.st);
   return e;
 }
@@ -97,8 +97,8 @@ hipError_t iteration(Run& R, int x_prec, int x_id, double* d_hist) {
   const int P = R.prec;
   const bool samp = sample_iteration(R);
   hipError_t e = record(R, samp);
-  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape.wg, R.shape.r, R.st);
-  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape.wg, R.shape.r, R.st);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape, R.st);
+  if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape, R.st);
   if (e == hipSuccess) e = record(R, samp);
   if (e == hipSuccess) e = launch_finalize(R.bh, FIN_ALPHA, 0, 2, R.shape.wg, d_hist, R.hist_len, R.st);
   if (e == hipSuccess) e = launch_update_r(R.bh, P, kVecWG, R.st);
@@ -164,9 +164,9 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     for (int i = 0; i < window; ++i) {
       const bool samp = sample_iteration(R);
       hipError_t e = record(R, samp);
-      if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape64.wg, R.shape64.r, R.st);
+      if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape64, R.st);
       if (e == hipSuccess)
-        e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64.wg, R.shape64.r, R.st);
+        e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64, R.st);
       if (e == hipSuccess) e = record(R, samp);
       if (e == hipSuccess)
         e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, R.shape64.wg, d_hist, R.hist_len, R.st, kVecWG);
@@ -306,7 +306,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     pd.vec[V_B] = const_cast<void*>(probs[p].b);
     pd.vec[V_X] = probs[p].x;
     table[p] = pd;
-    R.bh.probs.push_back(HostProb{L->g.half, n, slot});
+    R.bh.probs.push_back(HostProb{L->g.half, n, slot, L->g.Xh});
     max_half = std::max(max_half, L->g.half);
     slot += n;
   }
@@ -336,10 +336,10 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     std::vector<const stag_lattice_s*> lats(R.lats.begin(), R.lats.end());
     const std::string key = tune_key(R.bh, lats, prm.prec);
     if (prm.autotune && !has_shape(key)) STAG_HIP_TRY(tune_batch(R.bh, key, prm.prec, st, nullptr, nullptr));
-    R.shape = lookup_shape(R.bh, key);
+    R.shape = lookup_shape(R.bh, key, prm.prec);
     // the FP64 launches of the true residual use the FP64 key's shape
     const std::string key64 = tune_key(R.bh, lats, P64);
-    R.shape64 = lookup_shape(R.bh, key64);
+    R.shape64 = lookup_shape(R.bh, key64, P64);
   }
 
   // ---- scalars ----
@@ -547,6 +547,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     o.dslash_sites = sites;
     o.dslash_wg = R.shape.wg;
     o.dslash_rhs = R.shape.r;
+    o.dslash_lds = R.shape.lds;
     if (first_bad == STAG_OK && done_status[s] != STAG_OK) first_bad = (stag_status)done_status[s];
   }
   if (first_bad != STAG_OK)

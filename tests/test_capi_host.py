@@ -118,21 +118,23 @@ def test_batch_argument_validation(lib):
 def test_tune_cache_roundtrip(lib, tmp_path):
     """The tuning table loads from and saves to JSON without a GPU; malformed entries are refused."""
     src = tmp_path / "tune.json"
-    src.write_text('{\n  "p2:28x28x28x96/1": [256, 1],\n  "p0:8x8x8x8/8": [128, 8]\n}\n')
+    # an entry without the LDS flag (older files) reads as unstaged
+    src.write_text('{\n  "p2:28x28x28x96/1": [256, 1, 1],\n  "p0:8x8x8x8/8": [128, 8]\n}\n')
     assert lib.stag_tune_cache_load(str(src).encode()) == 0
     out = tmp_path / "out.json"
     assert lib.stag_tune_cache_save(str(out).encode()) == 0
     text = out.read_text()
-    assert '"p2:28x28x28x96/1": [256, 1]' in text and '"p0:8x8x8x8/8": [128, 8]' in text
+    assert '"p2:28x28x28x96/1": [256, 1, 1]' in text and '"p0:8x8x8x8/8": [128, 8, 0]' in text
     bad = tmp_path / "bad.json"
-    bad.write_text('{\n  "p0:8x8x8x8/8": [100, 3]\n}\n')
-    assert lib.stag_tune_cache_load(str(bad).encode()) == 1
+    for entry in ("[100, 3]", "[256, 1, 2]"):
+        bad.write_text('{\n  "p0:8x8x8x8/8": %s\n}\n' % entry)
+        assert lib.stag_tune_cache_load(str(bad).encode()) == 1, entry
     assert lib.stag_tune_cache_load(str(tmp_path / "missing.json").encode()) == 1
     assert lib.stag_tune_cache_load(None) == 1
 
 
 def test_shape_arguments_validated(lib):
-    assert lib.stag_set_dslash_shape(None, 0, 1, 256, 1) == 1
+    assert lib.stag_set_dslash_shape(None, 0, 1, 256, 1, 0) == 1
     assert lib.stag_tune_dslash(None, 0, 1, None, None, 0, None, None) == 1
 
 

@@ -295,11 +295,17 @@ def test_dslash_full_size_48cubed_144_eight_rhs_sampled(gpu_lib):
         for r in range(nrhs):
             ref = dslash_at_sites(fat, lng, b[r], dims, par, sample)
             assert rel(out[r][sample], ref) <= 1e-12, (par, r)
+    # the LDS-staged shape at full size gives the same bits
+    lat.set_dslash_shape("f64", nrhs, 64, 4, 1)
+    assert np.array_equal(lat.dslash(bt, 1).cpu().numpy(), out)
     lat.set_dslash_shape("f64", nrhs, 0, 1)
 
 
 def test_dslash_identical_for_every_launch_shape(gpu_lib):
-    """Workgroup size and right-hand sides per lane change the schedule, not the arithmetic: bitwise equal."""
+    """Workgroup size, right-hand sides per lane and LDS staging change the schedule, not the arithmetic:
+    bitwise equal."""
+    from paper_1010_4782_amd._lib import StagError
+
     dims = (6, 4, 6, 8)
     print("dslash launch shapes", flush=True)
     lat, fat, lng = make(dims, seed=91, precs=("f64", "f16"))
@@ -308,16 +314,21 @@ def test_dslash_identical_for_every_launch_shape(gpu_lib):
         ref = None
         for wg in (64, 128, 256):
             for r in (1, 2, 4, 8):
-                lat.set_dslash_shape(prec, 8, wg, r)
-                out = lat.dslash(b, 1, prec=prec)
-                if ref is None:
-                    ref = out.clone()
-                assert torch.equal(out, ref), (prec, wg, r)
+                for lds in (0, 1):
+                    if lds and r * (wg + 3 * dims[0]) * {"f64": 48, "f16": 16}[prec] > 65536:
+                        with pytest.raises(StagError):  # the staged window would not fit in 64 KiB of LDS
+                            lat.set_dslash_shape(prec, 8, wg, r, lds)
+                        continue
+                    lat.set_dslash_shape(prec, 8, wg, r, lds)
+                    out = lat.dslash(b, 1, prec=prec)
+                    if ref is None:
+                        ref = out.clone()
+                    assert torch.equal(out, ref), (prec, wg, r, lds)
         lat.set_dslash_shape(prec, 8, 0, 1)
     assert rel(ref.cpu().numpy()[3], dslash_eo(fat, lng, b.cpu().numpy()[3], dims, 1)) > 0  # f16 result exists
     best, timed = lat.tune_dslash("f16", 8)
-    assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and len(timed) == 12
-    assert all(t[2] > 0 for t in timed)
+    assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and best[2] in (0, 1) and len(timed) == 24
+    assert all(t[3] > 0 for t in timed)
 
 
 def test_batched_solve_with_autotune(gpu_lib):
