@@ -6,9 +6,10 @@ A step is one pass of the whole hot path over the workload's synthetic input,
 which is resident in HBM before timing starts: pack the links (phases, signs and
 c_N folded; FP64 + the inner precision) and solve (4m^2 - D_eo D_oe) x = b with
 mixed-precision CG and FP64 reliable updates to true residual 1e-10.  The plain
-FP64 CG solve of the same system is timed once beside it.  Every Dslash launch of
-the timed steps is bracketed by HIP events on the solver's stream; their average
-duration gives the roofline figure.  Prints one JSON line.
+FP64 CG solve of the same system is timed once beside it.  The two Dslash launches
+of every 10th CG iteration of the timed steps are bracketed by HIP events on the
+solver's stream; their average duration gives the roofline figure.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -185,6 +186,71 @@ def run_learned_preconditioner(a, out_json):
     return 0
 
 
+def network_leg(a, p, mass, tol, rel_int, mp_s, fp64_s):
+    """Workload 5's third leg: mixed precision, multi-RHS and the learned preconditioner together.  The
+    network is trained on the workload-4 lattice (24^3x48, links drawn by the same recipe) at this
+    workload's mass, then its weights (which do not depend on the volume: the layers are gauge-covariant
+    stencils with site-independent channel weights) are loaded into a network on the large lattice.  The
+    solve is flexible CG with the network on all RHS, which hands each RHS to the mixed-precision CG when
+    its residual stalls."""
+    import torch
+
+    from paper_1010_4782_amd.stagcg import Lattice, Net
+    from stag_inputs import WORKLOADS, gaussian_source_device, workload_links
+
+    w4 = WORKLOADS[4]
+    dims4, _ = w4["lattices"][0]
+    npairs = a.train_pairs if a.train_pairs > 0 else 256
+    fat, lng = workload_links(4)
+    small = Lattice(dims4)
+    small.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0,
+                     precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
+    del fat, lng
+    bs = torch.empty((npairs, small.half, 3), dtype=torch.complex128, device="cuda")
+    xs = torch.empty_like(bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c0 in range(0, npairs, 8):
+        n = min(8, npairs - c0)
+        bs[c0:c0 + n] = gaussian_source_device(dims4, 5000 + c0, n)
+        xs[c0:c0 + n], _ = small.cg_solve(bs[c0:c0 + n].contiguous(), mass, tol=tol, prec=a.prec,
+                                          reliable_interval=rel_int, autotune=True)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net_s = Net(small, layers=w4["layers"], channels=w4["channels"], seed=1, hermitian=True)
+    t0 = time.perf_counter()
+    tinfo = net_s.train(bs, xs, epochs=a.epochs, batch=8, lr=a.lr, loss=a.loss, mass=mass)
+    t_train = time.perf_counter() - t0
+    print(f"# network trained on {dims4}: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} "
+          f"({npairs} pairs, {t_data:.1f} s data, {t_train:.1f} s training)", file=sys.stderr, flush=True)
+    weights = net_s.get_weights()
+    del bs, xs, net_s, small
+    lat = p["lat"]
+    lat.load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
+    net = Net(lat, layers=w4["layers"], channels=w4["channels"], seed=1, hermitian=True)
+    net.set_weights(weights)
+    kw = dict(tol=tol, prec=a.prec, reliable_interval=rel_int, net=net, stall_window=10, autotune=True)
+    lat.cg_solve(p["b"], mass, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, info = lat.cg_solve(p["b"], mass, **kw)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net.apply(p["b"][:1].contiguous())
+    torch.cuda.synchronize()
+    t_apply = time.perf_counter() - t1
+    res = {"solve_s": t_solve, "iters": max(i["iters"] for i in info), "fell_back": sum(i["fell_back"] for i in info),
+           "true_resid": max(i["true_resid"] for i in info), "network_apply_ms_per_rhs": 1e3 * t_apply,
+           "speedup_vs_mixed_only": mp_s / t_solve, "speedup_vs_fp64_cg": (fp64_s / t_solve) if fp64_s else None,
+           "training": {"lattice": list(dims4), "pairs": npairs, "epochs": a.epochs, "data_s": t_data,
+                        "train_s": t_train, "loss_first": tinfo["loss_first"], "loss_last": tinfo["loss_last"]}}
+    print(f"# network + mixed precision: {res['iters']} it, {t_solve:.3f} s, {res['fell_back']} RHS fell back",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def run_shard_demo(a):
     """One GPU's share of a t-decomposed Dslash (the design of a multi-GPU run, exercised on one GPU):
     P slabs of Lt/P slices, each with its two 3-slice faces copied in from its neighbours; the slab
@@ -268,10 +334,14 @@ def main(argv=None):
                          "record idles the GPU for a few us, so timing every iteration would slow the solve)")
     ap.add_argument("--no-long-su3", action="store_true",
                     help="store the three-hop links with all 18 reals instead of two rows (12 parameters)")
-    ap.add_argument("--train-pairs", type=int, default=0, help="workload 4: training pairs (0: the workload's 2000)")
-    ap.add_argument("--epochs", type=int, default=5, help="workload 4: training epochs")
-    ap.add_argument("--lr", type=float, default=2e-3, help="workload 4: Adam step size")
-    ap.add_argument("--loss", default="residual", choices=["residual", "solution"], help="workload 4: training loss")
+    ap.add_argument("--train-pairs", type=int, default=0,
+                    help="workloads 4 and 5: training pairs (0: 2000 for workload 4, 256 for workload 5)")
+    ap.add_argument("--epochs", type=int, default=5, help="workloads 4 and 5: training epochs")
+    ap.add_argument("--lr", type=float, default=2e-3, help="workloads 4 and 5: Adam step size")
+    ap.add_argument("--loss", default="residual", choices=["residual", "solution"],
+                    help="workloads 4 and 5: training loss")
+    ap.add_argument("--no-net", action="store_true",
+                    help="workload 5: skip the leg that adds the learned preconditioner")
     ap.add_argument("--shard-demo", type=int, default=0, metavar="P",
                     help="instead of the solve: split the workload's first lattice into P time slabs (one per GPU "
                          "of a multi-GPU run), exchange the 3-slice faces on this one GPU, apply the slab Dslash, "
@@ -420,6 +490,9 @@ def main(argv=None):
                                "avg_launch_us": avg_ms * 1e3, "gflops": gflops}
     if all(p["nrhs"] == 1 for p in probs):
         out["dslash_" + a.prec]["GBps_paper_count"] = paper_count_rate(a.prec, avg_ms)
+    if a.workload == 5 and not a.no_net:
+        out["with_network"] = network_leg(a, probs[0], masses[0], tol, rel_int, out["solve_s"],
+                                          out.get("fp64_solve_s"))
     out["copy_ceiling"] = copy_ceiling(torch)
     if not a.no_cpu_baseline and a.workload == 2:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
