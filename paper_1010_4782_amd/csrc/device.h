@@ -65,34 +65,61 @@ template <typename T> __device__ __forceinline__ gptr_w<T> as_global_w(void* p) 
 
 // ---- colour vectors ---------------------------------------------------------
 // f64: 3 x double2 (48 B); f32: 3 x float2 (24 B); f16: uint4 = 6 binary16 codes + binary32 scale (16 B).
-template <int P> __device__ __forceinline__ void load_spinor(const void* base, long s, Cx<typename RealOf<P>::T> v[3]);
+// NT = true: a non-temporal access, for vectors a kernel streams once (the vector updates of CG);
+// vectors that are read again (the Dslash's neighbours) use the default, which keeps them in L2.
+template <typename V, bool NT> __device__ __forceinline__ V ld(gptr<V> p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename V, bool NT> __device__ __forceinline__ void st(gptr_w<V> p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
-template <> __device__ __forceinline__ void load_spinor<P64>(const void* base, long s, Cx<double> v[3]) {
-  gptr<d2v> p = as_global<d2v>(base) + 3 * s;
+template <int P, bool NT = false>
+__device__ __forceinline__ void load_spinor(const void* base, long s, Cx<typename RealOf<P>::T> v[3]) {
+  if constexpr (P == P64) {
+    gptr<d2v> p = as_global<d2v>(base) + 3 * s;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    d2v w = p[c];
-    v[c] = Cx<double>{w.x, w.y};
+    for (int c = 0; c < 3; ++c) {
+      const d2v w = ld<d2v, NT>(p + c);
+      v[c] = Cx<double>{w.x, w.y};
+    }
+  } else if constexpr (P == P32) {
+    gptr<f2v> p = as_global<f2v>(base) + 3 * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const f2v w = ld<f2v, NT>(p + c);
+      v[c] = Cx<float>{w.x, w.y};
+    }
+  } else {
+    const u4v w = ld<u4v, NT>(as_global<u4v>(base) + s);
+    const float sc = __uint_as_float(w.w);
+    v[0] = unpack_h2(w.x, sc);
+    v[1] = unpack_h2(w.y, sc);
+    v[2] = unpack_h2(w.z, sc);
   }
 }
-template <> __device__ __forceinline__ void load_spinor<P32>(const void* base, long s, Cx<float> v[3]) {
-  gptr<f2v> p = as_global<f2v>(base) + 3 * s;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    f2v w = p[c];
-    v[c] = Cx<float>{w.x, w.y};
+
+// Colour-vector loads for the Dslash, which keeps FP16 link matrices in code units and folds the
+// link's scale into the vector instead: v = (link scale x vector scale) x codes, one multiply per
+// component instead of one per matrix element.  For FP32 and FP64 (no scales) these are the plain loads.
+template <int P>
+__device__ __forceinline__ void load_spinor_ls(const void* base, long s, float lsc, Cx<typename RealOf<P>::T> v[3]) {
+  if constexpr (P == P16) {
+    const u4v w = as_global<u4v>(base)[s];
+    const float sc = __uint_as_float(w.w) * lsc;
+    v[0] = unpack_h2(w.x, sc);
+    v[1] = unpack_h2(w.y, sc);
+    v[2] = unpack_h2(w.z, sc);
+  } else {
+    load_spinor<P>(base, s, v);
   }
-}
-template <> __device__ __forceinline__ void load_spinor<P16>(const void* base, long s, Cx<float> v[3]) {
-  const u4v w = as_global<u4v>(base)[s];
-  const float sc = __uint_as_float(w.w);
-  v[0] = unpack_h2(w.x, sc);
-  v[1] = unpack_h2(w.y, sc);
-  v[2] = unpack_h2(w.z, sc);
 }
 
 // The same reads from a colour-vector array staged in LDS (index s relative to the staged window).
-template <int P> __device__ __forceinline__ void load_spinor_lds(const char* base, int s, Cx<typename RealOf<P>::T> v[3]) {
+template <int P>
+__device__ __forceinline__ void load_spinor_lds(const char* base, int s, float lsc, Cx<typename RealOf<P>::T> v[3]) {
   if constexpr (P == P64) {
     const d2v* p = reinterpret_cast<const d2v*>(base) + 3 * s;
 #pragma unroll
@@ -103,7 +130,7 @@ template <int P> __device__ __forceinline__ void load_spinor_lds(const char* bas
     for (int c = 0; c < 3; ++c) v[c] = Cx<float>{p[c].x, p[c].y};
   } else {
     const u4v w = reinterpret_cast<const u4v*>(base)[s];
-    const float sc = __uint_as_float(w.w);
+    const float sc = __uint_as_float(w.w) * lsc;
     v[0] = unpack_h2(w.x, sc);
     v[1] = unpack_h2(w.y, sc);
     v[2] = unpack_h2(w.z, sc);
@@ -111,35 +138,31 @@ template <int P> __device__ __forceinline__ void load_spinor_lds(const char* bas
 }
 
 // Store and return the stored (rounded) value in v.
-template <int P> __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]);
-
-template <> __device__ __forceinline__ void store_spinor<P64>(void* base, long s, Cx<double> v[3]) {
-  gptr_w<d2v> p = as_global_w<d2v>(base) + 3 * s;
+template <int P, bool NT = false>
+__device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]) {
+  if constexpr (P == P64) {
+    gptr_w<d2v> p = as_global_w<d2v>(base) + 3 * s;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = d2v{v[c].re, v[c].im};
-}
-template <> __device__ __forceinline__ void store_spinor<P32>(void* base, long s, Cx<float> v[3]) {
-  gptr_w<f2v> p = as_global_w<f2v>(base) + 3 * s;
+    for (int c = 0; c < 3; ++c) st<d2v, NT>(p + c, d2v{v[c].re, v[c].im});
+  } else if constexpr (P == P32) {
+    gptr_w<f2v> p = as_global_w<f2v>(base) + 3 * s;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = f2v{v[c].re, v[c].im};
-}
-template <> __device__ __forceinline__ void store_spinor<P16>(void* base, long s, Cx<float> v[3]) {
-  float m = 0.f;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-  uint4 w;
-  if (m > 0.f) {
-    w.x = pack_h2(v[0].re / m, v[0].im / m);
-    w.y = pack_h2(v[1].re / m, v[1].im / m);
-    w.z = pack_h2(v[2].re / m, v[2].im / m);
+    for (int c = 0; c < 3; ++c) st<f2v, NT>(p + c, f2v{v[c].re, v[c].im});
   } else {
-    w.x = w.y = w.z = 0u;
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    unsigned w0 = 0u, w1 = 0u, w2 = 0u;
+    if (m > 0.f) {
+      w0 = pack_h2(v[0].re / m, v[0].im / m);
+      w1 = pack_h2(v[1].re / m, v[1].im / m);
+      w2 = pack_h2(v[2].re / m, v[2].im / m);
+    }
+    st<u4v, NT>(as_global_w<u4v>(base) + s, u4v{w0, w1, w2, __float_as_uint(m)});
+    v[0] = unpack_h2(w0, m);
+    v[1] = unpack_h2(w1, m);
+    v[2] = unpack_h2(w2, m);
   }
-  w.w = __float_as_uint(m);
-  as_global_w<u4v>(base)[s] = u4v{w.x, w.y, w.z, w.w};
-  v[0] = unpack_h2(w.x, m);
-  v[1] = unpack_h2(w.y, m);
-  v[2] = unpack_h2(w.z, m);
 }
 
 // ---- packed links -----------------------------------------------------------
@@ -317,10 +340,11 @@ template <> __device__ __forceinline__ void raw_spinor_load<P32>(const void* bas
 template <> __device__ __forceinline__ void raw_spinor_load<P16>(const void* base, long s, RawSpinor<P16>& r) {
   r.w = as_global<u4v>(base)[s];
 }
+// lsc: the FP16 link scale folded into the vector (see load_spinor_ls); ignored for FP32 / FP64.
 template <int P>
-__device__ __forceinline__ void raw_spinor_decode(const RawSpinor<P>& r, Cx<typename RealOf<P>::T> v[3]) {
+__device__ __forceinline__ void raw_spinor_decode(const RawSpinor<P>& r, float lsc, Cx<typename RealOf<P>::T> v[3]) {
   if constexpr (P == P16) {
-    const float sc = __uint_as_float(r.w.w);
+    const float sc = __uint_as_float(r.w.w) * lsc;
     v[0] = unpack_h2(r.w.x, sc);
     v[1] = unpack_h2(r.w.y, sc);
     v[2] = unpack_h2(r.w.z, sc);
@@ -410,13 +434,18 @@ __device__ __forceinline__ int long_sign(const Site& s, const Geo& g, int mu, bo
 }
 
 // ---- reductions ---------------------------------------------------------------
-// Deterministic block sum of N doubles per thread; the result is valid in thread 0.
-template <int N, int MAXW = 4>
-__device__ __forceinline__ void block_sum(double v[N], double* lds /* >= N * MAXW */) {
+// Sum over the 64 lanes of a wave (butterfly of shuffles; every lane ends with the same sum).
+template <int N> __device__ __forceinline__ void wave_sum(double v[N]) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, kWave);
+}
+
+// Deterministic block sum of N doubles per thread; the result is valid in thread 0.
+template <int N, int MAXW = 4>
+__device__ __forceinline__ void block_sum(double v[N], double* lds /* >= N * MAXW */) {
+  wave_sum<N>(v);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int nw = blockDim.x / kWave;
   if (nw == 1) return;
