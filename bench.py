@@ -406,15 +406,16 @@ def main(argv=None):
     solve_time = [0.0]
 
     def dslash_rate(infos, prec):
-        """Algorithmic GB/s of the inner-iteration Dslash launches (plain and xpay averaged)."""
+        """Algorithmic GB/s of the inner-iteration Dslash launches (plain and xpay averaged).  The bytes
+        are the compulsory ones of the whole batch: each lattice's links once per launch, whatever the
+        launch shape (a shape with fewer RHS per lane than the lattice has re-reads them: that is not
+        counted), plus every RHS's input and output vectors (and half a vector for the xpay read)."""
         ms = sum(i[0]["dslash_ms"] for i in infos)
         calls = sum(i[0]["dslash_calls"] for i in infos)
-        r = infos[0][0]["dslash_rhs"]
         per_launch = 0.0
         for p in probs:
-            groups = p["nrhs"] // r
-            site = link_bytes_per_site(prec, not a.no_long_su3) + r * (2 * VEC[prec]) + r * VEC[prec] / 2.0
-            per_launch += p["lat"].half * groups * site
+            site = link_bytes_per_site(prec, not a.no_long_su3) + p["nrhs"] * 2.5 * VEC[prec]
+            per_launch += p["lat"].half * site
         avg = ms / max(calls, 1)
         sites = sum(p["lat"].half * p["nrhs"] for p in probs)
         return per_launch / (avg * 1e-3) / 1e9, avg, per_launch, calls, sites * FLOPS_PER_SITE / (avg * 1e-3) / 1e9

@@ -478,15 +478,24 @@ def test_dslash_slab_loopback_equals_unsplit(gpu_lib, prec, long_su3):
     S = dims[0] * dims[1] * dims[2] // 2
     Lt = dims[3]
     b = torch.from_numpy(gaussian_source(dims, 133, 2)).cuda()
-    for par in (0, 1):
-        ref = lat.dslash(b, par, prec=prec)
-        for lt in (4, 8):
-            for t0 in range(0, Lt, lt):
-                # the slab's extended input: slices t0-3 .. t0+lt+2 (mod Lt), faces copied from the neighbours
-                rows = torch.cat([torch.arange(((t0 + k) % Lt) * S, ((t0 + k) % Lt + 1) * S) for k in range(-3, lt + 3)])
-                ext = b[:, rows.cuda(), :].contiguous()
-                out = lat.dslash_slab(ext, par, t0, lt, prec=prec)
-                assert torch.equal(out, ref[:, t0 * S:(t0 + lt) * S, :]), (par, lt, t0)
+    refs = {}
+    # the default shape, then both RHS on one lane with the x/y neighbour window staged in LDS (the slab's
+    # input has 6 more slices than its output: the window is indexed in the input's sites)
+    for shape in (None, (256, 2, 1)):
+        if shape:
+            lat.set_dslash_shape(prec, 2, *shape)
+        for par in (0, 1):
+            ref = lat.dslash(b, par, prec=prec)
+            assert torch.equal(refs.setdefault(par, ref), ref), (par, shape)
+            for lt in (4, 8):
+                for t0 in range(0, Lt, lt):
+                    # the slab's extended input: slices t0-3 .. t0+lt+2 (mod Lt), faces copied from the neighbours
+                    rows = torch.cat([torch.arange(((t0 + k) % Lt) * S, ((t0 + k) % Lt + 1) * S)
+                                      for k in range(-3, lt + 3)])
+                    ext = b[:, rows.cuda(), :].contiguous()
+                    out = lat.dslash_slab(ext, par, t0, lt, prec=prec)
+                    assert torch.equal(out, ref[:, t0 * S:(t0 + lt) * S, :]), (par, lt, t0, shape)
+    lat.set_dslash_shape(prec, 2, 0, 1)
     from paper_1010_4782_amd.stagcg import StagError
 
     with pytest.raises(StagError):  # odd t0: the slab would change the even-odd parity of its sites
