@@ -332,6 +332,9 @@ def main(argv=None):
     ap.add_argument("--profile-every", type=int, default=10,
                     help="bracket the Dslash launches of every k-th CG iteration with HIP events (each event "
                          "record idles the GPU for a few us, so timing every iteration would slow the solve)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shape instead of timing the candidates (for "
+                         "counter-collection runs, where every dispatch is serialised and timings mean nothing)")
     ap.add_argument("--no-long-su3", action="store_true",
                     help="store the three-hop links with all 18 reals instead of two rows (12 parameters)")
     ap.add_argument("--train-pairs", type=int, default=0,
@@ -398,7 +401,7 @@ def main(argv=None):
             t_s = time.perf_counter()
             xs, inf = cg_solve_batch(batch, tol=tol, prec=prec, reliable_interval=rel_int, profile=profile,
                                      max_iter=a.max_iter, max_restarts=0 if a.max_iter else 5,
-                                     raise_on_fail=a.max_iter == 0, autotune=True)
+                                     raise_on_fail=a.max_iter == 0, autotune=not a.no_autotune)
             solve_time[0] += time.perf_counter() - t_s  # the call synchronises before returning
             infos.append(inf)
         return infos

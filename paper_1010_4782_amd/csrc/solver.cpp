@@ -432,8 +432,11 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
       std::vector<char> parked(nslots, 0);
       const double drop2 = prm.reliable_delta > 0.0 ? prm.reliable_delta * prm.reliable_delta : 0.0;
       for (;;) {
-        for (int i = 0; i < prm.check_interval; ++i) STAG_HIP_TRY(iteration(R, x_prec, x_id, d_hist));
-        since += prm.check_interval;
+        // a batch ends where the next interval-driven reliable update is due, so that it comes after
+        // exactly reliable_interval iterations, not at the next multiple of check_interval
+        const int batch = std::min(prm.check_interval, std::max(1, prm.reliable_interval - since));
+        for (int i = 0; i < batch; ++i) STAG_HIP_TRY(iteration(R, x_prec, x_id, d_hist));
+        since += batch;
         STAG_HIP_TRY(pull_scal(R, "poll-mp"));
         // Slots that stopped (apparent convergence, residual drop, iteration cap) wait for a
         // reliable update; once reliable_interval iterations have passed, every running slot does.
@@ -454,11 +457,13 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
         }
         const bool interval_due = since >= prm.reliable_interval;
         if (!any_wait && !interval_due) continue;
-        if (interval_due) {
+        if (interval_due)
           for (int s = 0; s < nslots; ++s)
             if (R.h_scal[s].state == 0) R.h_scal[s].state = 1;
-          since = 0;
-        }
+        // the interval restarts once every running slot is being updated (always, for one RHS)
+        bool any_running = false;
+        for (int s = 0; s < nslots; ++s) any_running |= R.h_scal[s].state == 0;
+        if (!any_running) since = 0;
         STAG_HIP_TRY(push_scal(R));
         // reliable update (slots in state 1): x += x_lo, r = b - M x in FP64, r_lo = r, and
         // restore <d, r> = |r|^2 for the new residual.

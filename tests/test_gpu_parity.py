@@ -148,6 +148,24 @@ def test_cg_mixed_precision_true_residual(gpu_lib, prec):
         assert true_residual(lambda v: apply_m(fat, lng, v, dims, mr), b[r], x[r]) <= 1.05e-10
 
 
+def test_reliable_update_interval_is_exact(gpu_lib):
+    """With the residual-drop trigger off, the FP64 reliable update comes every reliable_interval inner
+    iterations, even when that is not a multiple of the polling interval (20 vs 16 here)."""
+    dims = (8, 8, 8, 8)
+    print("reliable interval 8^4", flush=True)
+    lat, fat, lng = make(dims, seed=33, precs=("f64", "f16"))
+    b = gaussian_source(dims, 34, 1)
+    m = 0.05
+    x, info = lat.cg_solve(torch.from_numpy(b).cuda(), m, tol=1e-10, prec="f16", reliable_interval=20,
+                           reliable_delta=0.0, check_interval=16)
+    it, nrel = info[0]["iters"], info[0]["n_reliable"]
+    assert info[0]["converged"] == 1 and it >= 40, info[0]
+    # one update per 20 iterations, plus at most one at apparent convergence (a multiple of 16 would give
+    # one per 32)
+    assert it // 20 <= nrel <= it // 20 + 2, (it, nrel)
+    assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[0], x.cpu().numpy()[0]) <= 1.05e-10
+
+
 def test_cg_batched_uneven_lattices(gpu_lib):
     from paper_1010_4782_amd.stagcg import cg_solve_batch
 
