@@ -1,0 +1,72 @@
+"""Host logic of bench.py that runs without a GPU: the one-GPU guard, the byte accounting behind the
+roofline figures, the traffic record's source check, and the CPU-baseline leg on a tiny lattice."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr or "single MI355X" in res.stderr
+    assert res.stdout == ""
+
+
+def test_compulsory_bytes_per_site():
+    # FP64: 8 one-hop matrices of 9 complex doubles, 8 three-hop ones (6 complex stored, or 9), 48 B in and out
+    assert bench.dslash_bytes_per_site("f64", long12=True) == 8 * 144 + 8 * 96 + 2 * 48 == 2016
+    assert bench.dslash_bytes_per_site("f64", long12=False) == 16 * 144 + 2 * 48
+    # FP16: binary16 matrices, one binary32 scale per site for each of the two link kinds, 16 B vectors
+    assert bench.dslash_bytes_per_site("f16", long12=True) == 8 * 36 + 8 * 24 + 8 + 2 * 16 == 520
+    assert bench.dslash_bytes_per_site("f16", xpay=True, long12=True) == 536
+    assert bench.dslash_bytes_per_site("f32", long12=True) == 8 * 72 + 8 * 48 + 2 * 24
+
+
+def test_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
+    """The committed counter summary is used only while the kernel sources hash to the recorded value
+    and the long-link storage matches."""
+    path = os.path.join(ROOT, "profiles", "dslash_f16_28x28x28x96_traffic.json")
+    rec = json.load(open(path))
+    got = bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"])
+    assert got == rec["traffic_bytes_per_launch"]
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), not rec["long_su3"]) is None
+    assert bench.measured_traffic("f16", (4, 4, 4, 4), True) is None  # no record for this lattice
+    # a record whose hash does not match the sources is ignored
+    fake_root = tmp_path / "root"
+    (fake_root / "profiles").mkdir(parents=True)
+    for f in rec["source_files"]:
+        dst = fake_root / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(os.path.join(ROOT, f), "rb").read() + b"\n// changed\n")
+    (fake_root / "profiles" / os.path.basename(path)).write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"]) is None
+
+
+def test_cpu_baseline_leg_on_a_tiny_lattice():
+    from stag_inputs import fat_field, gaussian_source, random_su3_field
+
+    dims = (4, 4, 4, 4)
+    fat = fat_field(dims, 1)
+    lng = random_su3_field(dims, 2)
+    b = gaussian_source(dims, 3)[0]
+    cb = bench.cpu_baseline(fat, lng, b, dims, 0.1, 100)
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "s"
+    assert cb["per_iteration_s"] > 0 and np.isclose(cb["value"], 100 * cb["per_iteration_s"])
+
+
+@pytest.mark.parametrize("argv", [["--workload", "9"], ["--prec", "f64"]])
+def test_bad_arguments_are_rejected(argv):
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True, text=True,
+                         timeout=120)
+    assert res.returncode != 0
