@@ -466,7 +466,7 @@ def main(argv=None):
         "mp_reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
         "mp_true_resid": max(x["true_resid"] for inf in last for x in inf),
         "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"],
-                         "lds_stage": last[0][0]["dslash_lds"]},
+                         "lds_stage": last[0][0]["dslash_lds"], "tile_order": last[0][0]["dslash_order"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(a.prec, d0, not a.no_long_su3) if len(probs) == 1 and probs[0]["nrhs"] == 1 else None,

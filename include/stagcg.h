@@ -113,7 +113,8 @@ typedef struct {
   double dslash_sites;       /* profile>0: output sites x RHS processed per timed launch, averaged */
   int32_t dslash_wg;         /* launch shape used by the inner-iteration Dslash: sites per workgroup */
   int32_t dslash_rhs;        /* ... right-hand sides per lane */
-  int32_t dslash_lds;        /* ... and LDS staging of the x/y neighbour window (1) or not (0) */
+  int32_t dslash_lds;        /* ... LDS staging of the x/y neighbour window (1) or not (0) */
+  int32_t dslash_order;      /* ... and the tile order (0 lattice order, 1 XCD blocks) */
 } stag_cg_info;
 
 /* A Dslash launch shape and its measured time. */
@@ -124,6 +125,10 @@ typedef struct {
                                 [first - 3 Lx/2, last + 3 Lx/2] into LDS and reads its x and y
                                 neighbours from there (same result); needs
                                 rhs_per_lane x (wg + 3 Lx) x bytes-per-vector <= 64 KiB */
+  int32_t tile_order;        /* 0: workgroups take tiles in lattice order (t slowest); 1: the z extent
+                                is cut into 8 blocks, one per XCD, and each XCD sweeps t through its
+                                block, so that its L2 still holds the t-neighbour slices; needs Lz
+                                divisible by 8 and wg dividing Ly x Lx / 2.  Same result */
   double us;                 /* average launch time (stag_tune_dslash), 0 if not timed */
 } stag_shape;
 
@@ -208,13 +213,12 @@ stag_status stag_cg_solve_batch(int32_t nprob, const stag_problem* probs, const 
  * precision `prec` on this lattice (on library-owned scratch vectors, on `stream`), keeps the fastest
  * for later stag_dslash / stag_cg_solve calls with the same key, and returns it in *best; if all is
  * non-NULL, up to max_all timed candidates are written there and their count to *n_all.
- * stag_set_dslash_shape pins a shape for the key (wg = 0 removes the entry; a shape whose LDS window
- * does not fit is STAG_ERR_ARG).  The table is process-wide;
+ * stag_set_dslash_shape pins *shape (host; its us is ignored) for the key; shape NULL or shape->wg = 0
+ * removes the entry; a combination stag_shape rules out is STAG_ERR_ARG.  The table is process-wide;
  * stag_tune_cache_save / _load write and read it as JSON (path: a host C string). */
 stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, stag_shape* best, stag_shape* all,
                              int32_t max_all, int32_t* n_all, void* stream);
-stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane,
-                                  int32_t lds_stage);
+stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, const stag_shape* shape);
 stag_status stag_tune_cache_save(const char* path);
 stag_status stag_tune_cache_load(const char* path);
 

@@ -64,6 +64,7 @@ class StagInfo(C.Structure):
         ("dslash_wg", C.c_int32),
         ("dslash_rhs", C.c_int32),
         ("dslash_lds", C.c_int32),
+        ("dslash_order", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -71,7 +72,8 @@ class StagInfo(C.Structure):
 
 
 class StagShape(C.Structure):
-    _fields_ = [("wg", C.c_int32), ("rhs_per_lane", C.c_int32), ("lds_stage", C.c_int32), ("us", C.c_double)]
+    _fields_ = [("wg", C.c_int32), ("rhs_per_lane", C.c_int32), ("lds_stage", C.c_int32), ("tile_order", C.c_int32),
+                ("us", C.c_double)]
 
 
 class StagProblem(C.Structure):
@@ -128,7 +130,7 @@ SIGNATURES = {
                                       C.POINTER(StagInfo), C.c_void_p]),
     "stag_tune_dslash": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(StagShape), C.POINTER(StagShape),
                                    C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
-    "stag_set_dslash_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "stag_set_dslash_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(StagShape)]),
     "stag_tune_cache_save": (C.c_int, [C.c_char_p]),
     "stag_tune_cache_load": (C.c_int, [C.c_char_p]),
     "stag_net_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64,

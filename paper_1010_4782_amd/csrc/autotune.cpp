@@ -1,5 +1,6 @@
 // Autotuner for the Dslash launch shape: workgroup size (sites per workgroup),
-// right-hand sides per lane and LDS staging of the x/y neighbour window.  Candidates are timed with HIP events on the caller's
+// right-hand sides per lane, LDS staging of the x/y neighbour window and the
+// tile order (lattice order or XCD blocks).  Candidates are timed with HIP events on the caller's
 // stream on the real buffers of the call; winners are kept per key
 // (lattice shapes, right-hand sides, storage precision) in memory and can be saved
 // to / loaded from a small JSON file.
@@ -60,7 +61,7 @@ DslashShape lookup_shape(const BatchHost& bh, const std::string& key, int prec) 
   if (it != g_table.end()) {
     DslashShape s = it->second;
     s.r = std::min(s.r, rhs_divisor(bh));
-    if (!dslash_shape_valid(bh, prec, s)) s.lds = 0;  // a loaded table entry whose window does not fit
+    if (!dslash_shape_valid(bh, prec, s)) s.lds = s.order = 0;  // a loaded entry that does not fit this batch
     return s;
   }
   return heuristic(bh, prec);
@@ -96,8 +97,8 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
   const int reps = 5;
   for (int wg : {64, 128, 256}) {
     for (int r = 1; r <= rmax && e == hipSuccess; r *= 2) {
-      for (int lds = 0; lds < 2; ++lds) {
-        const DslashShape sh{wg, r, lds};
+      for (int v = 0; v < 4; ++v) {
+        const DslashShape sh{wg, r, v & 1, v >> 1};
         if (!dslash_shape_valid(bh, prec, sh)) continue;
         for (int w = 0; w < 2 && e == hipSuccess; ++w)
           e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, sh, st);
@@ -134,14 +135,16 @@ bool save_table(const char* path) {
   f << "{\n";
   size_t i = 0;
   for (const auto& kv : g_table) {
-    f << "  \"" << kv.first << "\": [" << kv.second.wg << ", " << kv.second.r << ", " << kv.second.lds << "]"
+    f << "  \"" << kv.first << "\": [" << kv.second.wg << ", " << kv.second.r << ", " << kv.second.lds << ", "
+      << kv.second.order << "]"
       << (++i < g_table.size() ? ",\n" : "\n");
   }
   f << "}\n";
   return (bool)f;
 }
 
-// Reads the format save_table writes: one "key": [wg, r, lds] entry per line (lds may be absent: 0).
+// Reads the format save_table writes: one "key": [wg, r, lds, order] entry per line (lds and order may
+// be absent: 0).
 bool load_table(const char* path, int* n_loaded) {
   std::ifstream f(path);
   if (!f) return false;
@@ -154,12 +157,13 @@ bool load_table(const char* path, int* n_loaded) {
     const size_t q1 = line.find('"', q0 + 1);
     const size_t b0 = line.find('[', q1);
     if (q1 == std::string::npos || b0 == std::string::npos) return false;
-    int wg = 0, r = 0, lds = 0;
-    const int got = std::sscanf(line.c_str() + b0, "[%d , %d , %d]", &wg, &r, &lds);
+    int wg = 0, r = 0, lds = 0, order = 0;
+    const int got = std::sscanf(line.c_str() + b0, "[%d , %d , %d , %d]", &wg, &r, &lds, &order);
     if (got < 2) return false;
-    if ((wg != 64 && wg != 128 && wg != 256) || (r != 1 && r != 2 && r != 4 && r != 8) || (lds != 0 && lds != 1))
+    if ((wg != 64 && wg != 128 && wg != 256) || (r != 1 && r != 2 && r != 4 && r != 8) || (lds != 0 && lds != 1) ||
+        (order != 0 && order != 1))
       return false;
-    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r, lds};
+    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r, lds, order};
     ++n;
   }
   std::lock_guard<std::mutex> lk(g_mu);

@@ -173,7 +173,7 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
     sc[r] = z;
   }
   STAG_HIP_TRY(hipMemcpyAsync(e.dev, e.host, off_part, hipMemcpyHostToDevice, st));
-  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh});
+  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh, pd.g.L[1], pd.g.L[2]});
   bh.d_probs = reinterpret_cast<const ProbDev*>(e.dev);
   bh.d_scal = reinterpret_cast<Scal*>(e.dev + off_scal);
   bh.d_partial = reinterpret_cast<double*>(e.dev + off_part);
@@ -463,13 +463,13 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
   if (s != STAG_OK) return s;
   float best_us = 0.f;
   for (const auto& t : timed)
-    if (t.first.wg == b.wg && t.first.r == b.r && t.first.lds == b.lds) best_us = t.second;
-  if (best) *best = stag_shape{b.wg, b.r, b.lds, best_us};
+    if (t.first.wg == b.wg && t.first.r == b.r && t.first.lds == b.lds && t.first.order == b.order) best_us = t.second;
+  if (best) *best = stag_shape{b.wg, b.r, b.lds, b.order, best_us};
   if (all) {
     int n = 0;
     for (const auto& t : timed) {
       if (n >= max_all) break;
-      all[n++] = stag_shape{t.first.wg, t.first.r, t.first.lds, t.second};
+      all[n++] = stag_shape{t.first.wg, t.first.r, t.first.lds, t.first.order, t.second};
     }
     if (n_all) *n_all = n;
   }
@@ -477,24 +477,31 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
   STAG_GUARD_END
 }
 
-stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, int32_t wg, int32_t rhs_per_lane,
-                                  int32_t lds_stage) {
+stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs, const stag_shape* shape) {
   STAG_GUARD_BEGIN
   if (!lat) return arg_error("lattice is NULL");
   if (nrhs < 1) return arg_error("nrhs must be >= 1");
   if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
-  if (wg != 0 && wg != 64 && wg != 128 && wg != 256) return arg_error("wg must be 0, 64, 128 or 256");
-  if (wg != 0 && rhs_per_lane != 1 && rhs_per_lane != 2 && rhs_per_lane != 4 && rhs_per_lane != 8)
-    return arg_error("rhs_per_lane must be 1, 2, 4 or 8");
-  if (wg != 0 && nrhs % rhs_per_lane) return arg_error("rhs_per_lane must divide nrhs");
-  if (lds_stage != 0 && lds_stage != 1) return arg_error("lds_stage must be 0 or 1");
   BatchHost bh;
-  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0, lat->g.Xh});
+  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0, lat->g.Xh, lat->g.L[1], lat->g.L[2]});
   bh.long12 = lat->g.long12 != 0;
-  const DslashShape sh{wg, rhs_per_lane, lds_stage};
-  if (wg != 0 && !dslash_shape_valid(bh, prec, sh))
-    return arg_error("the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
-  pin_shape(single_key(bh, lat, prec), sh);
+  const std::string key = single_key(bh, lat, prec);
+  if (!shape || shape->wg == 0) {
+    pin_shape(key, DslashShape{0, 1, 0, 0});
+    return STAG_OK;
+  }
+  const int wg = shape->wg, r = shape->rhs_per_lane;
+  if (wg != 64 && wg != 128 && wg != 256) return arg_error("wg must be 0, 64, 128 or 256");
+  if (r != 1 && r != 2 && r != 4 && r != 8) return arg_error("rhs_per_lane must be 1, 2, 4 or 8");
+  if (nrhs % r) return arg_error("rhs_per_lane must divide nrhs");
+  if (shape->lds_stage != 0 && shape->lds_stage != 1) return arg_error("lds_stage must be 0 or 1");
+  if (shape->tile_order != 0 && shape->tile_order != 1) return arg_error("tile_order must be 0 or 1");
+  const DslashShape sh{wg, r, shape->lds_stage, shape->tile_order};
+  if (!dslash_shape_valid(bh, prec, sh))
+    return arg_error(sh.order ? "tile_order 1 needs Lz divisible by 8 and wg dividing Ly x Lx / 2 (and, staged, "
+                                "an LDS window within 64 KiB)"
+                              : "the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
+  pin_shape(key, sh);
   return STAG_OK;
   STAG_GUARD_END
 }

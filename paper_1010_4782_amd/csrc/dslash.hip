@@ -44,9 +44,31 @@ extern __shared__ __align__(16) char dslash_window[];
 
 __host__ __device__ constexpr int window_margin(int xh) { return 3 * xh; }
 
+// Tile order 1 (XCD blocks): the z extent is cut into kZBlocks blocks, one per XCD, and the workgroups
+// of an XCD (a contiguous range of positions, xcd_remap) sweep t through their block: the colour
+// vectors of the t +-1, +-3 neighbours of a block's slices are then still in that XCD's L2 when they are
+// read again, which the lattice order (t slowest) loses once a slice of all RHS outgrows L2.  Tiles stay
+// contiguous site ranges (a whole number of them per z plane), so every tile is computed exactly as in
+// the lattice order; the shape is valid only where that holds (xcd_order_ok).
+constexpr int kZBlocks = 8;
+__host__ __device__ inline bool xcd_order_ok(int ny, int nz, int xh, int wg) {
+  return nz % kZBlocks == 0 && (ny * xh) % wg == 0;
+}
+__device__ __forceinline__ int xcd_block_tile(int pos, const Geo& g, int wg) {
+  const int tpz = g.L[1] * g.Xh / wg;  // tiles per z plane
+  const int zbs = g.L[2] / kZBlocks;
+  const int j = pos % tpz;
+  int rest = pos / tpz;
+  const int zi = rest % zbs;
+  rest /= zbs;
+  const int t = rest % g.L[3];
+  const int zb = rest / g.L[3];
+  return (t * g.L[2] + zb * zbs + zi) * tpz + j;
+}
+
 template <int P, int R, int EPI, bool C12, int PF, bool LDS>
 __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
-                                                   int b_id, int gate) {
+                                                   int b_id, int gate, int order) {
   static_assert(!(LDS && PF > 0), "the staged path uses the plain link loop");
   using T = typename RealOf<P>::T;
   __shared__ double lds[R * 4];
@@ -56,9 +78,10 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
   const Geo g = pd->g;
   const int local = bid - B.block_start[p];
   const int groups = B.groups[p];
-  const int tile = local / groups;
-  const int r0 = (local - tile * groups) * R;
+  const int pos = local / groups;
+  const int r0 = (local - pos * groups) * R;
   const int nrhs = pd->nrhs, slot0 = pd->slot0;
+  const int tile = order ? xcd_block_tile(pos, g, blockDim.x) : pos;
 
   bool on[R];
   bool any = false;
@@ -237,26 +260,26 @@ Batch make_batch(const BatchHost& bh, int wg, int r) {
 
 template <int P, int R, bool C12, bool LDS>
 static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
-                           int gate, int wg, size_t lds_bytes, hipStream_t st) {
+                           int gate, int wg, int order, size_t lds_bytes, hipStream_t st) {
   constexpr int PF = (R == 1 && !LDS) ? dslash_pf<P>() : 0;
   constexpr int PF64 = (R == 1 && !LDS) ? dslash_pf<P64>() : 0;
   switch (epi) {
     case EPI_PLAIN:
-      k_dslash<P, R, EPI_PLAIN, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate);
+      k_dslash<P, R, EPI_PLAIN, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate, order);
       break;
     case EPI_XPAY_DOT:
       k_dslash<P, R, EPI_XPAY_DOT, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
-                                                                            gate);
+                                                                            gate, order);
       break;
     case EPI_RESID:
       if (P != P64) return hipErrorInvalidValue;
       k_dslash<P64, R, EPI_RESID, C12, PF64, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
-                                                                             gate);
+                                                                             gate, order);
       break;
     case EPI_XPAY:
       if (P != P64) return hipErrorInvalidValue;
       k_dslash<P64, R, EPI_XPAY, C12, PF64, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id,
-                                                                            gate);
+                                                                            gate, order);
       break;
     default:
       return hipErrorInvalidValue;
@@ -266,12 +289,12 @@ static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int i
 
 template <int P, bool C12, bool LDS>
 static hipError_t dslash_p(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
-                           int gate, int wg, int r, size_t lds_bytes, hipStream_t st) {
+                           int gate, int wg, int r, int order, size_t lds_bytes, hipStream_t st) {
   switch (r) {
-    case 1: return dslash_r<P, 1, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
-    case 2: return dslash_r<P, 2, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
-    case 4: return dslash_r<P, 4, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
-    case 8: return dslash_r<P, 8, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, lds_bytes, st);
+    case 1: return dslash_r<P, 1, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, order, lds_bytes, st);
+    case 2: return dslash_r<P, 2, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, order, lds_bytes, st);
+    case 4: return dslash_r<P, 4, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, order, lds_bytes, st);
+    case 8: return dslash_r<P, 8, C12, LDS>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, wg, order, lds_bytes, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -280,10 +303,14 @@ template <int P>
 static hipError_t dslash_pc(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                             int gate, const DslashShape& sh, bool c12, size_t lds_bytes, hipStream_t st) {
   if (c12)
-    return sh.lds ? dslash_p<P, true, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, lds_bytes, st)
-                  : dslash_p<P, true, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, 0, st);
-  return sh.lds ? dslash_p<P, false, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, lds_bytes, st)
-                : dslash_p<P, false, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r, 0, st);
+    return sh.lds ? dslash_p<P, true, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
+                                            sh.order, lds_bytes, st)
+                  : dslash_p<P, true, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
+                                             sh.order, 0, st);
+  return sh.lds ? dslash_p<P, false, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
+                                           sh.order, lds_bytes, st)
+                : dslash_p<P, false, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
+                                            sh.order, 0, st);
 }
 
 // The LDS window holds wg + 6 Xh sites (of the widest lattice of the batch) per RHS of a lane.
@@ -297,6 +324,10 @@ size_t dslash_lds_bytes(const BatchHost& bh, int prec, const DslashShape& sh) {
 bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh) {
   if (sh.wg != 64 && sh.wg != 128 && sh.wg != 256) return false;
   if (sh.r != 1 && sh.r != 2 && sh.r != 4 && sh.r != 8) return false;
+  if (sh.order != 0 && sh.order != 1) return false;
+  if (sh.order)
+    for (const auto& p : bh.probs)
+      if (!xcd_order_ok(p.ny, p.nz, p.xh, sh.wg)) return false;
   return dslash_lds_bytes(bh, prec, sh) <= kMaxDslashLds;
 }
 

@@ -20,6 +20,7 @@ struct HostProb {
   int nrhs;
   int slot0;
   int xh = 0;  // Lx / 2 (width of the LDS window margin of a staged Dslash)
+  int ny = 0, nz = 0;  // Ly, Lz (whether the XCD-block tile order fits the lattice)
 };
 
 constexpr size_t kMaxDslashLds = 64 * 1024;  // LDS a staged Dslash workgroup may use
@@ -43,6 +44,7 @@ struct DslashShape {
   int wg = 256;
   int r = 1;
   int lds = 0;  // 1: stage the x and y neighbour colour vectors of a workgroup's sites in LDS
+  int order = 0;  // 1: XCD-block tile order (each XCD sweeps t through one z block)
 };
 
 // Bytes of LDS a staged launch of this shape needs (0 if unstaged), and whether it fits.

@@ -306,7 +306,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     pd.vec[V_B] = const_cast<void*>(probs[p].b);
     pd.vec[V_X] = probs[p].x;
     table[p] = pd;
-    R.bh.probs.push_back(HostProb{L->g.half, n, slot, L->g.Xh});
+    R.bh.probs.push_back(HostProb{L->g.half, n, slot, L->g.Xh, L->g.L[1], L->g.L[2]});
     max_half = std::max(max_half, L->g.half);
     slot += n;
   }
@@ -553,6 +553,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     o.dslash_wg = R.shape.wg;
     o.dslash_rhs = R.shape.r;
     o.dslash_lds = R.shape.lds;
+    o.dslash_order = R.shape.order;
     if (first_bad == STAG_OK && done_status[s] != STAG_OK) first_bad = (stag_status)done_status[s];
   }
   if (first_bad != STAG_OK)

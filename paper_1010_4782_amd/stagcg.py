@@ -158,18 +158,23 @@ class Lattice:
         return out
 
     def tune_dslash(self, prec: str = "f64", nrhs: int = 1, stream=None):
-        """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, us), ...])."""
+        """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, tile_order, us), ...])."""
         best = StagShape()
-        all_ = (StagShape * 32)()
+        all_ = (StagShape * 64)()
         n = C.c_int32(0)
-        check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 32, C.byref(n),
+        check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 64, C.byref(n),
                                      _stream(stream)), "stag_tune_dslash")
-        return ((best.wg, best.rhs_per_lane, best.lds_stage, best.us),
-                [(all_[i].wg, all_[i].rhs_per_lane, all_[i].lds_stage, all_[i].us) for i in range(n.value)])
+        def tup(s):
+            return (s.wg, s.rhs_per_lane, s.lds_stage, s.tile_order, s.us)
 
-    def set_dslash_shape(self, prec: str, nrhs: int, wg: int, rhs_per_lane: int, lds_stage: int = 0):
-        check(lib().stag_set_dslash_shape(self._h, PREC[prec], int(nrhs), int(wg), int(rhs_per_lane),
-                                          int(lds_stage)), "stag_set_dslash_shape")
+        return tup(best), [tup(all_[i]) for i in range(n.value)]
+
+    def set_dslash_shape(self, prec: str, nrhs: int, wg: int, rhs_per_lane: int = 1, lds_stage: int = 0,
+                         tile_order: int = 0):
+        """Pin a Dslash launch shape for (this lattice, nrhs, prec); wg = 0 removes the pinned shape."""
+        sh = StagShape(int(wg), int(rhs_per_lane), int(lds_stage), int(tile_order), 0.0)
+        check(lib().stag_set_dslash_shape(self._h, PREC[prec], int(nrhs), C.byref(sh) if wg else None),
+              "stag_set_dslash_shape")
 
     def cg_solve(self, b: torch.Tensor, mass, x0: torch.Tensor | None = None, raise_on_fail=True, stream=None,
                  **params):

@@ -33,23 +33,29 @@ def test_compulsory_bytes_per_site():
 
 
 def test_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
-    """The committed counter summary is used only while the kernel sources hash to the recorded value
-    and the long-link storage matches."""
-    path = os.path.join(ROOT, "profiles", "dslash_f16_28x28x28x96_traffic.json")
-    rec = json.load(open(path))
-    got = bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"])
-    assert got == rec["traffic_bytes_per_launch"]
+    """A counter summary is used only while the kernel sources hash to the value recorded with it and the
+    long-link storage matches (checked on a copy of the sources, so that the test does not depend on
+    whether the committed record was taken on the current kernels)."""
+    import hashlib
+
+    rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_f16_28x28x28x96_traffic.json")))
+    root = tmp_path / "root"
+    (root / "profiles").mkdir(parents=True)
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        dst = root / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        data = open(os.path.join(ROOT, f), "rb").read()
+        dst.write_bytes(data)
+        h.update(data)
+    mine = dict(rec, source_sha256=h.hexdigest(), traffic_bytes_per_launch=123.0)
+    (root / "profiles" / "dslash_f16_28x28x28x96_traffic.json").write_text(json.dumps(mine))
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"]) == 123.0
     assert bench.measured_traffic("f16", (28, 28, 28, 96), not rec["long_su3"]) is None
     assert bench.measured_traffic("f16", (4, 4, 4, 4), True) is None  # no record for this lattice
-    # a record whose hash does not match the sources is ignored
-    fake_root = tmp_path / "root"
-    (fake_root / "profiles").mkdir(parents=True)
-    for f in rec["source_files"]:
-        dst = fake_root / f
-        dst.parent.mkdir(parents=True, exist_ok=True)
-        dst.write_bytes(open(os.path.join(ROOT, f), "rb").read() + b"\n// changed\n")
-    (fake_root / "profiles" / os.path.basename(path)).write_text(json.dumps(rec))
-    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    changed = root / rec["source_files"][0]
+    changed.write_bytes(changed.read_bytes() + b"\n// changed\n")
     assert bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"]) is None
 
 

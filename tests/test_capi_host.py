@@ -124,9 +124,9 @@ def test_tune_cache_roundtrip(lib, tmp_path):
     out = tmp_path / "out.json"
     assert lib.stag_tune_cache_save(str(out).encode()) == 0
     text = out.read_text()
-    assert '"p2:28x28x28x96/1": [256, 1, 1]' in text and '"p0:8x8x8x8/8": [128, 8, 0]' in text
+    assert '"p2:28x28x28x96/1": [256, 1, 1, 0]' in text and '"p0:8x8x8x8/8": [128, 8, 0, 0]' in text
     bad = tmp_path / "bad.json"
-    for entry in ("[100, 3]", "[256, 1, 2]"):
+    for entry in ("[100, 3]", "[256, 1, 2]", "[64, 1, 0, 2]"):
         bad.write_text('{\n  "p0:8x8x8x8/8": %s\n}\n' % entry)
         assert lib.stag_tune_cache_load(str(bad).encode()) == 1, entry
     assert lib.stag_tune_cache_load(str(tmp_path / "missing.json").encode()) == 1
@@ -134,7 +134,7 @@ def test_tune_cache_roundtrip(lib, tmp_path):
 
 
 def test_shape_arguments_validated(lib):
-    assert lib.stag_set_dslash_shape(None, 0, 1, 256, 1, 0) == 1
+    assert lib.stag_set_dslash_shape(None, 0, 1, None) == 1
     assert lib.stag_tune_dslash(None, 0, 1, None, None, 0, None, None) == 1
 
 

@@ -313,8 +313,10 @@ def test_dslash_full_size_48cubed_144_eight_rhs_sampled(gpu_lib):
         for r in range(nrhs):
             ref = dslash_at_sites(fat, lng, b[r], dims, par, sample)
             assert rel(out[r][sample], ref) <= 1e-12, (par, r)
-    # the LDS-staged shape at full size gives the same bits
+    # the LDS-staged shape and the XCD-block tile order at full size give the same bits
     lat.set_dslash_shape("f64", nrhs, 64, 4, 1)
+    assert np.array_equal(lat.dslash(bt, 1).cpu().numpy(), out)
+    lat.set_dslash_shape("f64", nrhs, 64, 4, 0, 1)
     assert np.array_equal(lat.dslash(bt, 1).cpu().numpy(), out)
     lat.set_dslash_shape("f64", nrhs, 0, 1)
 
@@ -346,7 +348,31 @@ def test_dslash_identical_for_every_launch_shape(gpu_lib):
     assert rel(ref.cpu().numpy()[3], dslash_eo(fat, lng, b.cpu().numpy()[3], dims, 1)) > 0  # f16 result exists
     best, timed = lat.tune_dslash("f16", 8)
     assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and best[2] in (0, 1) and len(timed) == 24
-    assert all(t[3] > 0 for t in timed)
+    assert best[3] == 0 and all(t[3] == 0 and t[4] > 0 for t in timed)  # the XCD-block order does not fit Lz = 6
+
+
+def test_xcd_block_tile_order_is_bitwise_equal(gpu_lib):
+    """The XCD-block tile order only changes which workgroup takes which tile: every shape gives the bits
+    of the lattice order, and a lattice or workgroup size it does not fit is refused."""
+    from paper_1010_4782_amd._lib import StagError
+
+    dims = (8, 16, 8, 4)  # Lz = 8 blocks of one z plane; Ly x Lx / 2 = 64 sites per z plane
+    print("dslash tile order", flush=True)
+    lat, fat, lng = make(dims, seed=93, precs=("f64", "f16"))
+    b = torch.from_numpy(gaussian_source(dims, 94, 4)).cuda()
+    for prec in ("f64", "f16"):
+        lat.set_dslash_shape(prec, 4, 64, 1)
+        ref = lat.dslash(b, 0, prec=prec)
+        for r in (1, 2, 4):
+            for lds in (0, 1):
+                lat.set_dslash_shape(prec, 4, 64, r, lds, 1)
+                assert torch.equal(lat.dslash(b, 0, prec=prec), ref), (prec, r, lds)
+        with pytest.raises(StagError):
+            lat.set_dslash_shape(prec, 4, 128, 1, 0, 1)  # 128 does not divide the 64 sites of a z plane
+        lat.set_dslash_shape(prec, 4, 0, 1)
+    assert rel(ref.cpu().numpy()[1], dslash_eo(fat, lng, b.cpu().numpy()[1], dims, 0)) > 0
+    x, info = lat.cg_solve(b, 0.05, tol=1e-10, prec="f16")
+    assert all(i["converged"] == 1 for i in info)
 
 
 def test_batched_solve_with_autotune(gpu_lib):
