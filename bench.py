@@ -488,7 +488,9 @@ def main(argv=None):
         out["fp64_true_resid"] = max(x["true_resid"] for inf in i64 for x in inf)
         out["speedup_vs_fp64_cg"] = t64 / (ms_per_step / 1e3)
         out["dslash_f64"] = {"GBps": gbs64, "frac_of_hbm_peak": gbs64 / HBM_PEAK_GBPS, "avg_launch_us": avg64 * 1e3,
-                             "gflops": gf64}
+                             "gflops": gf64, "shape": {"wg": i64[0][0]["dslash_wg"], "rhs_per_lane": i64[0][0]["dslash_rhs"],
+                                                       "lds_stage": i64[0][0]["dslash_lds"],
+                                                       "tile_order": i64[0][0]["dslash_order"]}}
         print(f"# fp64 CG: {out['fp64_iters']} it, {t64:.3f} s, Dslash {gbs64:.0f} GB/s", file=sys.stderr, flush=True)
     out["dslash_" + a.prec] = {"GBps": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBPS,
                                "avg_launch_us": avg_ms * 1e3, "gflops": gflops}

@@ -80,9 +80,9 @@ bool has_shape(const std::string& key) {
   return g_table.count(key) != 0;
 }
 
-// Time every candidate shape on the batch's Dslash (V_D -> V_T, output parity 1, plain epilogue).
+// Time every candidate shape on the batch's Dslash (in_id -> out_id, output parity 1, plain epilogue).
 hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hipStream_t st, DslashShape* best_out,
-                      std::vector<std::pair<DslashShape, float>>* all) {
+                      std::vector<std::pair<DslashShape, float>>* all, int in_id, int out_id) {
   const int rmax = rhs_divisor(bh);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
@@ -101,10 +101,10 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
         const DslashShape sh{wg, r, v & 1, v >> 1};
         if (!dslash_shape_valid(bh, prec, sh)) continue;
         for (int w = 0; w < 2 && e == hipSuccess; ++w)
-          e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, sh, st);
+          e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int i = 0; i < reps && e == hipSuccess; ++i)
-          e = launch_dslash(bh, prec, EPI_PLAIN, 1, V_D, V_T, 0, 0, 3, sh, st);
+          e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;

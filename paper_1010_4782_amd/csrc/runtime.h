@@ -78,7 +78,7 @@ DslashShape lookup_shape(const BatchHost& bh, const std::string& key, int prec);
 void pin_shape(const std::string& key, const DslashShape& s);
 bool has_shape(const std::string& key);
 hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hipStream_t st, DslashShape* best,
-                      std::vector<std::pair<DslashShape, float>>* all);
+                      std::vector<std::pair<DslashShape, float>>* all, int in_id = V_D, int out_id = V_T);
 bool save_table(const char* path);
 bool load_table(const char* path, int* n_loaded);
 

@@ -337,8 +337,11 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     const std::string key = tune_key(R.bh, lats, prm.prec);
     if (prm.autotune && !has_shape(key)) STAG_HIP_TRY(tune_batch(R.bh, key, prm.prec, st, nullptr, nullptr));
     R.shape = lookup_shape(R.bh, key, prm.prec);
-    // the FP64 launches of the true residual use the FP64 key's shape
+    // the FP64 launches of the true residual use the FP64 key's shape; a mixed-precision solve tunes it on
+    // the FP64 buffers those launches use (x, read only, into the residual scratch)
     const std::string key64 = tune_key(R.bh, lats, P64);
+    if (prm.autotune && mixed && !has_shape(key64))
+      STAG_HIP_TRY(tune_batch(R.bh, key64, P64, st, nullptr, nullptr, V_X, V_TMPO));
     R.shape64 = lookup_shape(R.bh, key64, P64);
   }
 
