@@ -323,7 +323,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--prec", default="f16", choices=["f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
@@ -404,7 +404,11 @@ def main(argv=None):
                                      raise_on_fail=a.max_iter == 0, autotune=not a.no_autotune)
             solve_time[0] += time.perf_counter() - t_s  # the call synchronises before returning
             infos.append(inf)
+            if "source_sites" in w:  # propagators: the pion correlator of every source is part of the step
+                corr.append((probs[0]["lat"].pion_correlator(xs[0], m), xs[0]))
         return infos
+
+    corr = []
 
     solve_time = [0.0]
 
@@ -444,6 +448,7 @@ def main(argv=None):
         print(f"# step {i}: max iterations per batch {its}, worst true resid {res:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    mp_corr = corr[-1] if corr else None  # the last timed mixed-precision step's correlator
     ms_per_step = 1e3 * elapsed / a.steps
     flat = [inf for infos in all_infos for inf in infos]
     achieved, avg_ms, bytes_per_launch, d_calls, gflops = dslash_rate(flat, a.prec)
@@ -499,6 +504,20 @@ def main(argv=None):
     if a.workload == 5 and not a.no_net:
         out["with_network"] = network_leg(a, probs[0], masses[0], tol, rel_int, out["solve_s"],
                                           out.get("fp64_solve_s"))
+    if mp_corr is not None:
+        C, x0 = mp_corr
+        torch.cuda.synchronize()
+        Ch = C.cpu().numpy()
+        d0 = probs[0]["dims"]
+        diag = []
+        for s_, (sx, sy, sz, st) in enumerate(w["source_sites"]):
+            cb = (sx + d0[0] * (sy + d0[1] * (sz + d0[2] * st))) // 2
+            diag.append(sum(float(x0[3 * s_ + c, cb, c].real) for c in range(3)))
+        out["propagators"] = {
+            "sources": w["source_sites"], "correlator_t0_to_8": [list(map(float, row[:8])) for row in Ch],
+            "sum_rule_rel_err": max(abs(Ch[s_].sum() - diag[s_]) / diag[s_] for s_ in range(len(diag))),
+            "note": "C(t) = sum over time slice t of |G|^2, G_e = 2m chi, G_o = -D_oe chi; the sum over t equals "
+                    "sum_c chi^(c)(x0)_c"}
     out["copy_ceiling"] = copy_ceiling(torch)
     if not a.no_cpu_baseline and a.workload == 2:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)

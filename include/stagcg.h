@@ -183,6 +183,21 @@ stag_status stag_dslash(stag_lattice_t lat, int32_t out_parity, const void* in, 
 stag_status stag_dslash_slab(stag_lattice_t lat, int32_t out_parity, int32_t t0, int32_t lt, const void* in_ext,
                              void* out, int32_t nrhs, int32_t prec, void* stream);
 
+/* Time-slice sums for the staggered pion correlator of point-source propagators (the paper's closing
+ * remarks: the solver runs in production for hadron spectra).  For a source on an even site x0 with
+ * colour c, chi = (4m^2 - D_eo D_oe)^{-1} delta solves Eq. (3) and the propagator of M = 2m + D is
+ * G_e = 2m chi, G_o = -D_oe chi; the correlator C(t) sums |G|^2 over time slice t, the sink colour and
+ * the three source colours.  This call computes, for each group g of `group` consecutive right-hand
+ * sides of v and each time slice t,
+ *   out[g][t] = (accumulate ? out[g][t] : 0) + weight * sum_{r in g} sum_{sites of slice t} |v_r|^2,
+ * so that C = slice_norm2(chi, 3, 4m^2) followed by slice_norm2(D_oe chi, 3, 1, accumulate).  The sites
+ * of one slice and parity are a contiguous even-odd range, so v may hold either parity.
+ * v: device complex128 [nrhs][V/2][3]; out: device double [nrhs / group][Lt]; group divides nrhs.
+ * Summation order is fixed (same result for every call).  NULL pointers, group not dividing nrhs, a
+ * non-finite weight or accumulate not 0/1: STAG_ERR_ARG. */
+stag_status stag_slice_norm2(stag_lattice_t lat, const void* v, int32_t nrhs, int32_t group, double weight,
+                             int32_t accumulate, double* out, void* stream);
+
 /* out = M in = 4 m^2 in - D_eo D_oe in on even sites (Eq. (3)), FP64.
  * mass: host double[nrhs]; in, out: device complex128 [nrhs][V/2][3], not overlapping. */
 stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,

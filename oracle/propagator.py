@@ -21,22 +21,11 @@ from __future__ import annotations
 
 import numpy as np
 
+from stag_inputs import point_sources  # noqa: F401  (the unit sources are inputs, shared with the GPU side)
+
 from .cg import cg
 from .dslash import NAIK_COEFF, apply_m, dslash_eo
-from .geometry import cb_of_site, embed, parity
-
-
-def point_sources(dims, sites) -> np.ndarray:
-    """For each even site (x, y, z, t) in sites, the three unit sources of its colours: [3 * len(sites)][V/2][3]."""
-    half = dims[0] * dims[1] * dims[2] * dims[3] // 2
-    out = np.zeros((3 * len(sites), half, 3), dtype=np.complex128)
-    for s, (x, y, z, t) in enumerate(sites):
-        if (x + y + z + t) % 2:
-            raise ValueError(f"source site {(x, y, z, t)} is odd; the even-site solve needs an even source")
-        cb = cb_of_site(x, y, z, t, dims)
-        for c in range(3):
-            out[3 * s + c, cb, c] = 1.0
-    return out
+from .geometry import embed, parity
 
 
 def even_solutions(fat, lng, dims, mass: float, sources, tol: float = 1e-12, naik: float = NAIK_COEFF):

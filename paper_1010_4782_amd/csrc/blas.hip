@@ -556,4 +556,38 @@ hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, in
   return hipGetLastError();
 }
 
+// Time-slice sums for the pion correlator of point-source propagators:
+//   out[g][t] = (accumulate ? out[g][t] : 0) + weight * sum_{r in group g} sum_{i < slice} |v_r(t * slice + i)|^2
+// The sites of one time slice and parity are the contiguous even-odd range [t * slice, (t + 1) * slice).
+// One workgroup per (group, slice) sums its slice in a fixed order: the result does not depend on the
+// launch.  FP64 colour vectors.
+__global__ __launch_bounds__(kMaxWG) void k_slice_norm2(const char* v, long half, int slice, int lt, int group,
+                                                        double weight, int accumulate, double* out) {
+  __shared__ double lds[4];
+  const int t = blockIdx.x % lt, g = blockIdx.x / lt;
+  double acc[1] = {0.0};
+  for (int r = 0; r < group; ++r) {
+    const char* base = v + (long)(g * group + r) * half * spinor_bytes(P64);
+    for (int i = threadIdx.x; i < slice; i += blockDim.x) {
+      Cx<double> c[3];
+      load_spinor<P64, true>(base, (long)t * slice + i, c);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[0] += c[k].re * c[k].re + c[k].im * c[k].im;
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) {
+    const double val = weight * acc[0];
+    out[blockIdx.x] = accumulate ? out[blockIdx.x] + val : val;
+  }
+}
+
+hipError_t launch_slice_norm2(const void* v, long half, int slice, int lt, int ngroups, int group, double weight,
+                              int accumulate, double* out, hipStream_t st) {
+  if (ngroups == 0) return hipSuccess;
+  k_slice_norm2<<<ngroups * lt, kMaxWG, 0, st>>>(reinterpret_cast<const char*>(v), half, slice, lt, group, weight,
+                                                 accumulate, out);
+  return hipGetLastError();
+}
+
 }  // namespace stag

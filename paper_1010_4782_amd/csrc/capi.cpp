@@ -422,6 +422,22 @@ stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in,
   STAG_GUARD_END
 }
 
+stag_status stag_slice_norm2(stag_lattice_t lat, const void* v, int32_t nrhs, int32_t group, double weight,
+                             int32_t accumulate, double* out, void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (!v || !out) return arg_error("v and out must not be NULL");
+  if (nrhs < 1 || group < 1 || nrhs % group) return arg_error("group must be >= 1 and divide nrhs >= 1");
+  if (!std::isfinite(weight)) return arg_error("weight must be finite");
+  if (accumulate != 0 && accumulate != 1) return arg_error("accumulate must be 0 or 1");
+  const int lt = lat->dims[3];
+  STAG_HIP_TRY(launch_slice_norm2(v, lat->g.half, lat->g.half / lt, lt, nrhs / group, group, weight, accumulate, out,
+                                  reinterpret_cast<hipStream_t>(stream)));
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
 stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b, void* x, int32_t nrhs,
                           const stag_cg_params* prm, stag_cg_info* info, void* stream) {
   STAG_GUARD_BEGIN

@@ -55,6 +55,8 @@ hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, in
 
 // Vector stages of the solvers (every one is one launch over all slots of the batch).
 hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st);
+hipError_t launch_slice_norm2(const void* v, long half, int slice, int lt, int ngroups, int group, double weight,
+                              int accumulate, double* out, hipStream_t st);
 // producer_wg: sites per block of the launch that wrote the first partial kind; aux_wg (0: the same)
 // for the further kinds of multi-kind modes.
 hipError_t launch_finalize(const BatchHost& bh, int what, int kind, int gate, int producer_wg, double* hist,

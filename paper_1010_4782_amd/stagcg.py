@@ -146,6 +146,33 @@ class Lattice:
                                      nrhs, PREC[prec], _stream(stream)), "stag_dslash_slab")
         return out
 
+    def slice_norm2(self, v: torch.Tensor, group: int = 1, weight: float = 1.0, out=None, accumulate=False,
+                    stream=None) -> torch.Tensor:
+        """out[g][t] (+)= weight * sum of |v|^2 over time slice t and the RHS of group g (float64 [n/group][Lt])."""
+        nrhs = self._vec(v, "v")
+        if nrhs % group:
+            raise ValueError("group must divide the number of right-hand sides")
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs out")
+            out = torch.empty((nrhs // group, self.dims[3]), dtype=torch.float64, device=v.device)
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or \
+                tuple(out.shape) != (nrhs // group, self.dims[3]):
+            raise ValueError(f"out must be a contiguous float64 CUDA tensor of shape {(nrhs // group, self.dims[3])}")
+        check(lib().stag_slice_norm2(self._h, v.data_ptr(), nrhs, int(group), float(weight), 1 if accumulate else 0,
+                                     out.data_ptr(), _stream(stream)), "stag_slice_norm2")
+        return out
+
+    def pion_correlator(self, chi: torch.Tensor, mass: float, stream=None) -> torch.Tensor:
+        """C[s][t] of point-source propagators from their even-site solutions chi (3 consecutive RHS, the
+        source colours, per source): G_e = 2m chi and G_o = -D_oe chi, C(t) = sum over slice t of |G|^2."""
+        nrhs = self._vec(chi, "chi")
+        if nrhs % 3:
+            raise ValueError("chi holds three right-hand sides (source colours) per source")
+        odd = self.dslash(chi, 1, stream=stream)
+        C = self.slice_norm2(chi, 3, 4.0 * mass * mass, stream=stream)
+        return self.slice_norm2(odd, 3, 1.0, out=C, accumulate=True, stream=stream)
+
     def apply_m(self, x: torch.Tensor, mass, out=None, stream=None) -> torch.Tensor:
         nrhs = self._vec(x, "in")
         masses = [float(mass)] * nrhs if not isinstance(mass, (list, tuple)) else [float(m) for m in mass]

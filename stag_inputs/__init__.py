@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "GELL_MANN", "WORKLOADS", "su3_near_identity", "random_su3_field",
     "fat_field", "gaussian_source", "gaussian_source_device", "gaussian_full_field", "random_gauge_transform",
-    "workload", "workload_links", "workload_sources", "half_volume", "volume",
+    "workload", "workload_links", "workload_sources", "point_sources", "half_volume", "volume",
 ]
 
 
@@ -64,6 +64,11 @@ WORKLOADS = {
             masses=[0.01], fat="fat", tol=1e-10, train_pairs=2000, layers=4, channels=8),
     5: dict(name="48^3x144 x 8 RHS", lattices=[((48, 48, 48, 144), 8)], masses=[0.0062],
             fat="fat", tol=1e-10),
+    # point sources at four times (three colours each) on one gauge field: the propagators of a
+    # spectrum calculation and their pion correlator
+    6: dict(name="28^3x96 point-source propagators", lattices=[((28, 28, 28, 96), 12)], masses=[0.0062],
+            fat="fat", tol=1e-10, reliable_interval=50,
+            source_sites=[(0, 0, 0, 0), (0, 0, 0, 24), (0, 0, 0, 48), (0, 0, 0, 72)]),
 }
 NAIK_COEFF = -1.0 / 24.0
 
@@ -179,5 +184,21 @@ def workload_links(i: int, lattice_index: int = 0):
 def workload_sources(i: int, lattice_index: int = 0, nrhs: int | None = None) -> np.ndarray:
     w = WORKLOADS[i]
     dims, n = w["lattices"][lattice_index]
+    if "source_sites" in w:
+        return point_sources(dims, w["source_sites"])
     n = n if nrhs is None else nrhs
     return gaussian_source(dims, 1000 * i + 10 + 100 * lattice_index, n)
+
+
+def point_sources(dims, sites) -> np.ndarray:
+    """Unit sources delta_{n, site} delta_{a, c} for each even site in sites and colour c = 0, 1, 2:
+    complex128 [3 * len(sites)][V/2][3] (even-odd index cb = lex >> 1)."""
+    Lx, Ly, Lz, Lt = _check_dims(dims)
+    out = np.zeros((3 * len(sites), half_volume(dims), 3), dtype=np.complex128)
+    for s, (x, y, z, t) in enumerate(sites):
+        if (x + y + z + t) % 2:
+            raise ValueError(f"source site {(x, y, z, t)} is odd; the even-site solve needs an even source")
+        cb = (x + Lx * (y + Ly * (z + Lz * t))) // 2
+        for c in range(3):
+            out[3 * s + c, cb, c] = 1.0
+    return out

@@ -544,3 +544,40 @@ def test_dslash_slab_loopback_equals_unsplit(gpu_lib, prec, long_su3):
 
     with pytest.raises(StagError):  # odd t0: the slab would change the even-odd parity of its sites
         lat.dslash_slab(torch.zeros((1, 10 * S, 3), dtype=torch.complex128, device="cuda"), 0, 1, 4)
+
+
+def test_pion_correlator_of_point_source_propagators(gpu_lib):
+    """Point sources at two even sites (three colours each) solved on the GPU; the correlator from
+    stag_slice_norm2 and the GPU Dslash against the oracle, on the GPU's own solution (the sums) and on
+    the oracle's solution (the whole chain), plus the sum rule sum_t C(t) = sum_c chi^(c)(x0)_c."""
+    from oracle import geometry
+    from oracle.propagator import correlator, even_solutions, propagator
+    from stag_inputs import point_sources
+
+    dims = (4, 4, 4, 8)
+    m = 0.1
+    print("pion correlator 4^3x8", flush=True)
+    lat, fat, lng = make(dims, seed=321, precs=("f64", "f16"))
+    sites = [(0, 0, 0, 0), (1, 2, 3, 2)]
+    b = point_sources(dims, sites)
+    bt = torch.from_numpy(b).cuda()
+    chi, info = lat.cg_solve(bt, m, tol=1e-12)
+    assert all(i["converged"] == 1 for i in info)
+    C = lat.pion_correlator(chi, m).cpu().numpy()
+    chi_h = chi.cpu().numpy()
+    np.testing.assert_allclose(C, correlator(*propagator(fat, lng, dims, m, chi_h), dims), rtol=1e-12)
+    ref = correlator(*propagator(fat, lng, dims, m, even_solutions(fat, lng, dims, m, b, tol=1e-13)), dims)
+    np.testing.assert_allclose(C, ref, rtol=1e-9)
+    for s, site in enumerate(sites):
+        cb = geometry.cb_of_site(*site, dims)
+        assert C[s].sum() == pytest.approx(sum(chi_h[3 * s + c, cb, c].real for c in range(3)), rel=1e-10)
+    # the mixed-precision solve gives the same correlator to the accuracy of its solution
+    chi16, info16 = lat.cg_solve(bt, m, tol=1e-10, prec="f16")
+    np.testing.assert_allclose(lat.pion_correlator(chi16, m).cpu().numpy(), ref, rtol=1e-7)
+    # the sums honour group and accumulate; a group that does not divide nrhs is refused
+    one = lat.slice_norm2(chi, 1, 2.0).cpu().numpy()
+    np.testing.assert_allclose(one[0] + one[1] + one[2], lat.slice_norm2(chi, 3, 2.0).cpu().numpy()[0], rtol=1e-13)
+    from paper_1010_4782_amd._lib import StagError
+
+    with pytest.raises((StagError, ValueError)):
+        lat.slice_norm2(chi, 4)
