@@ -31,10 +31,36 @@ __device__ __forceinline__ void dslash_issue(int k, const Site& s, const Geo& g,
   raw_spinor_load<P>(in, nb, v);
 }
 
+// The same for R right-hand sides per lane: one link, the R colour vectors at its neighbour (only for
+// the active RHS; `on` is uniform over the workgroup).
+template <int P, bool C12, int R>
+__device__ __forceinline__ void dslash_issue_r(int k, const Site& s, const Geo& g, const char* lbase, long blk,
+                                               int lane, const char* in, long rstride_in, const bool on[R],
+                                               RawLink<P>& l, RawSpinor<P> v[R]) {
+  const int mu = k >> 2, j = k & 3;
+  const int nb = neighbour(s, g, mu, j < 2 ? g.h1[mu] : g.h3[mu], (j & 1) == 0);
+  const char* slot = lbase + link_slot_offset(P, C12, blk, k);
+  if (C12 && j >= 2)
+    raw_link_load<P, 2>(slot, lane, l);
+  else
+    raw_link_load<P, 3>(slot, lane, l);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (on[r]) raw_spinor_load<P>(in + r * rstride_in, nb, v[r]);
+}
+
 // Prefetch distance (links) of the single right-hand-side kernel, per storage precision, from a
 // sweep of 0-16 on the 28^3x96 lattice: the compiler's own schedule keeps 2-4 loads in flight,
 // and these distances are 6% (f16), 8% (f32) and 9% (f64) faster.
 template <int P> constexpr int dslash_pf() { return P == P16 ? 12 : (P == P32 ? 8 : 6); }
+// With several RHS per lane the link loads are pipelined too, over fewer links, since each stage holds
+// R colour vectors in flight.
+template <int P, int R> constexpr int dslash_pf_r() {
+  if (R == 1) return dslash_pf<P>();
+  if (P == P16) return R == 2 ? 8 : (R == 4 ? 4 : 2);
+  if (P == P32) return R == 2 ? 4 : (R == 4 ? 2 : 1);
+  return R == 2 ? 4 : (R == 4 ? 2 : 1);
+}
 
 // LDS staging (LDS = true): before the link loop a workgroup copies into LDS the colour vectors of
 // the window [c0 - 3 Xh, c0 + wg + 3 Xh) of its first site c0 (for each of its RHS); the x and y
@@ -145,7 +171,38 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
     // multiplied.  An empty volatile asm that takes the accumulators closes each stage: the
     // products of link k must be done before it and the loads issued after it cannot move above
     // it, so the compiler can neither hoist all loads to the top nor sink them to their uses.
-    static_assert(R == 1, "the pipelined path serves one right-hand side per lane");
+    if constexpr (R > 1) {
+      RawLink<P> lb[PF];
+      RawSpinor<P> vb[PF][R];
+#pragma unroll
+      for (int k = 0; k < PF; ++k)
+        dslash_issue_r<P, C12, R>(k, s, g, lbase, blk, lane, in, rstride_in, on, lb[k], vb[k]);
+#pragma unroll
+      for (int k = 0; k < kLinks; ++k) {
+        const int mu = k >> 2, j = k & 3;
+        Cx<T> u[9];
+        const float lsc = j < 2 ? sc_fat : sc_long;
+        if (C12 && j >= 2) {
+          raw_link_decode<P, 2>(lb[k % PF], 1.f, u);
+          rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv * (T)lsc);
+        } else {
+          raw_link_decode<P, 3>(lb[k % PF], 1.f, u);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!on[r]) continue;
+          Cx<T> v[3];
+          raw_spinor_decode<P>(vb[k % PF][r], lsc, v);
+          matvec_acc(u, v, acc[r]);
+        }
+        if (k + PF < kLinks)
+          dslash_issue_r<P, C12, R>(k + PF, s, g, lbase, blk, lane, in, rstride_in, on, lb[k % PF], vb[k % PF]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          asm volatile("" : "+v"(acc[r][0].re), "+v"(acc[r][0].im), "+v"(acc[r][1].re), "+v"(acc[r][1].im),
+                       "+v"(acc[r][2].re), "+v"(acc[r][2].im));
+      }
+    } else {
     RawLink<P> lb[PF];
     RawSpinor<P> vb[PF];
 #pragma unroll
@@ -167,6 +224,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
       if (k + PF < kLinks) dslash_issue<P, C12>(k + PF, s, g, lbase, blk, lane, in, lb[k % PF], vb[k % PF]);
       asm volatile("" : "+v"(acc[0][0].re), "+v"(acc[0][0].im), "+v"(acc[0][1].re), "+v"(acc[0][1].im),
                    "+v"(acc[0][2].re), "+v"(acc[0][2].im));
+    }
     }
   } else
 #pragma unroll
@@ -261,8 +319,8 @@ Batch make_batch(const BatchHost& bh, int wg, int r) {
 template <int P, int R, bool C12, bool LDS>
 static hipError_t dslash_r(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                            int gate, int wg, int order, size_t lds_bytes, hipStream_t st) {
-  constexpr int PF = (R == 1 && !LDS) ? dslash_pf<P>() : 0;
-  constexpr int PF64 = (R == 1 && !LDS) ? dslash_pf<P64>() : 0;
+  constexpr int PF = !LDS ? dslash_pf_r<P, R>() : 0;
+  constexpr int PF64 = !LDS ? dslash_pf_r<P64, R>() : 0;
   switch (epi) {
     case EPI_PLAIN:
       k_dslash<P, R, EPI_PLAIN, C12, PF, LDS><<<nblk, wg, lds_bytes, st>>>(B, out_par, in_id, out_id, x_id, b_id, gate, order);
