@@ -37,15 +37,15 @@ int rhs_divisor(const BatchHost& bh) {
   return r;
 }
 
-// Untuned default, from sweeps on 28^3x96 (1-8 RHS, every precision): one RHS per lane runs best in
-// 64-site workgroups; with several RHS, 4 per lane in 256-site workgroups with the LDS window staged is
-// the fastest or within 4% of it.
+// Untuned default, from sweeps on 28^3x96 (1-8 RHS, every precision): 64-site workgroups with as many
+// RHS per lane as divide every problem's count (up to 8), unstaged, lattice order.  With the link
+// pipeline of the multi-RHS kernels that is the fastest shape or within 3% of it for 4 and 8 RHS; at
+// 2 RHS FP32 gains 8% from LDS staging, which only the tuner finds.
 DslashShape heuristic(const BatchHost& bh, int prec) {
   DslashShape s;
-  s.r = std::min(rhs_divisor(bh), 4);
-  s.wg = s.r == 1 ? 64 : 256;
-  s.lds = s.r > 1 ? 1 : 0;
-  if (!dslash_shape_valid(bh, prec, s)) s.lds = 0;
+  s.r = rhs_divisor(bh);
+  s.wg = 64;
+  if (!dslash_shape_valid(bh, prec, s)) s = DslashShape{64, 1, 0, 0};
   return s;
 }
 

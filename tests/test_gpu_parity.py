@@ -386,7 +386,7 @@ def test_batched_solve_with_autotune(gpu_lib):
         probs.append((lat, torch.from_numpy(b).cuda(), [0.05] * nrhs, None))
         refs.append((fat, lng, dims, b))
     xs, infos = cg_solve_batch(probs, tol=1e-10, prec="f16", autotune=True)
-    assert infos[0]["dslash_rhs"] in (1, 2, 4)
+    assert infos[0]["dslash_rhs"] in (1, 2, 4, 8)
     k = 0
     for (fat, lng, dims, b), x in zip(refs, xs):
         x = x.cpu().numpy()
