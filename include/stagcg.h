@@ -91,7 +91,8 @@ typedef struct {
                                 per event, so k of 10 or more keeps the solve time representative */
   int32_t history_len;       /* record the first history_len (alpha, beta) pairs per RHS into history */
   double* history;           /* host [nrhs][history_len][2] or NULL */
-  int32_t autotune;          /* 1: time the Dslash launch shapes on first use of a (lattices, nrhs, prec) key */
+  int32_t autotune;          /* 1: time the Dslash launch shapes on first use of a (lattices, nrhs, prec) key
+                                (a mixed-precision solve also tunes the FP64 key of its reliable updates) */
   int32_t reserved[7];
 } stag_cg_params;
 
@@ -120,7 +121,8 @@ typedef struct {
 /* A Dslash launch shape and its measured time. */
 typedef struct {
   int32_t wg;                /* output sites per workgroup: 64, 128 or 256 */
-  int32_t rhs_per_lane;      /* right-hand sides each lane applies a loaded link to: 1, 2, 4 or 8 */
+  int32_t rhs_per_lane;      /* right-hand sides each lane applies a loaded link to: 1, 2, 4 or 8,
+                                dividing nrhs */
   int32_t lds_stage;         /* 1: the workgroup first copies the colour vectors of sites
                                 [first - 3 Lx/2, last + 3 Lx/2] into LDS and reads its x and y
                                 neighbours from there (same result); needs
