@@ -328,14 +328,14 @@ def test_dslash_identical_for_every_launch_shape(gpu_lib):
 
     dims = (6, 4, 6, 8)
     print("dslash launch shapes", flush=True)
-    lat, fat, lng = make(dims, seed=91, precs=("f64", "f16"))
+    lat, fat, lng = make(dims, seed=91, precs=("f64", "f32", "f16"))
     b = torch.from_numpy(gaussian_source(dims, 92, 8)).cuda()
-    for prec in ("f64", "f16"):
+    for prec in ("f64", "f32", "f16"):
         ref = None
         for wg in (64, 128, 256):
             for r in (1, 2, 4, 8):
                 for lds in (0, 1):
-                    if lds and r * (wg + 3 * dims[0]) * {"f64": 48, "f16": 16}[prec] > 65536:
+                    if lds and r * (wg + 3 * dims[0]) * {"f64": 48, "f32": 24, "f16": 16}[prec] > 65536:
                         with pytest.raises(StagError):  # the staged window would not fit in 64 KiB of LDS
                             lat.set_dslash_shape(prec, 8, wg, r, lds)
                         continue
