@@ -285,6 +285,9 @@ stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng
   lat->loaded = false;
   lat->g.long12 = c12 ? 1 : 0;
   lat->g.cn_inv = c12 ? 1.0 / naik_coeff : 0.0;
+  // FP64 is always packed; with FP16 requested too, the FP64 pack also computes the FP16 scales and the
+  // FP16 matrices are converted from the packed FP64 ones
+  const bool f16 = (prec_mask & STAG_PREC_BIT(P16)) != 0;
   for (int p = 0; p < 3; ++p) {
     if (!(prec_mask & STAG_PREC_BIT(p))) {
       for (auto& b : lat->links[p]) b.release();
@@ -293,11 +296,15 @@ stag_status stag_load_links(stag_lattice_t lat, const void* fat, const void* lng
     for (int par = 0; par < 2; ++par) {
       STAG_HIP_TRY(lat->links[p][par].ensure(padded / kWave * link_block_bytes(p, c12)));
       float* ls = nullptr;
-      if (p == P16) {
+      if (p == P16 || (p == P64 && f16)) {
         STAG_HIP_TRY(lat->lscale[par].ensure(padded * 2 * sizeof(float)));
         ls = reinterpret_cast<float*>(lat->lscale[par].ptr);
       }
-      STAG_HIP_TRY(launch_pack_links(p, fat, lng, naik_coeff, lat->g, lat->antiper, par, lat->links[p][par].ptr, ls, st));
+      if (p == P16)
+        STAG_HIP_TRY(launch_pack_f16_from_f64(lat->links[P64][par].ptr, ls, lat->g, lat->links[p][par].ptr, st));
+      else
+        STAG_HIP_TRY(launch_pack_links(p, fat, lng, naik_coeff, lat->g, lat->antiper, par, lat->links[p][par].ptr, ls,
+                                       st));
     }
   }
   lat->built = prec_mask;

@@ -89,9 +89,13 @@ hipError_t launch_fcg_beta_dot(const BatchHost& bh, int gate, int wg, hipStream_
 hipError_t launch_rd_dot(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);
 hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStream_t st);
 
-// Packing and conversions.
+// Packing and conversions.  launch_pack_links packs FP64 (with lscale non-NULL it also writes the FP16
+// scales) or FP32; FP16 comes from the packed FP64 matrices.
 hipError_t launch_pack_links(int prec, const void* fat, const void* lng, double naik, const Geo& g, int antiper,
                              int par, void* out, float* lscale, hipStream_t st);
+// FP16 packing from the FP64 packed matrices and the scales the FP64 pack wrote into lscale.
+hipError_t launch_pack_f16_from_f64(const void* packed64, const float* lscale, const Geo& g, void* out,
+                                    hipStream_t st);
 hipError_t launch_convert_from_f64(int prec, const void* in, void* out, long nsites, hipStream_t st);
 hipError_t launch_convert_to_f64(int prec, const void* in, void* out, long nsites, hipStream_t st);
 

@@ -86,21 +86,10 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
   const int lane = cb_raw & 63;
   float scale[2] = {0.f, 0.f};
   const bool c12 = g.long12 != 0;
-  if (P == P16) {
-    for (int k = 0; k < kLinks && live; ++k) {
-      double2 u[9];
-      folded_link(fat, lng, naik, g, antiper, s, k, u);
-      const int grp = (k >> 1) & 1;
-      const int nst = (c12 && grp) ? 6 : 9;  // stored entries (two rows of a compressed three-hop link)
-      double m = 0.0;
-#pragma unroll
-      for (int e = 0; e < 9; ++e)  // fixed trip count: u stays in registers
-        if (e < nst) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
-      scale[grp] = fmaxf(scale[grp], (float)m);  // float rounding of a max equals the max of the roundings
-    }
-    lscale[blk * 2 * kWave + lane] = scale[0];
-    lscale[blk * 2 * kWave + kWave + lane] = scale[1];
-  }
+  // FP64 with lscale: also compute the FP16 scales of the same matrices for k_pack_f16_from_f64, per
+  // output site the largest |re|, |im| over the stored entries of its eight one-hop and, separately, its
+  // eight three-hop matrices (rounded to binary32: the rounding of a max is the max of the roundings)
+  const bool scales64 = P == P64 && lscale != nullptr;
   for (int k = 0; k < kLinks; ++k) {
     double2 u[9];
     if (live) {
@@ -116,36 +105,77 @@ __global__ __launch_bounds__(256) void k_pack_links(const double2* fat, const do
 #pragma unroll
       for (int e = 0; e < 9; ++e)
         if (e < (two_rows ? 6 : 9)) o[e * kWave] = u[e];
-    } else if (P == P32) {
+      if (scales64 && live) {
+        double m = 0.0;
+#pragma unroll
+        for (int e = 0; e < 9; ++e)
+          if (e < (two_rows ? 6 : 9)) m = fmax(m, fmax(fabs(u[e].x), fabs(u[e].y)));
+        scale[(k >> 1) & 1] = fmaxf(scale[(k >> 1) & 1], (float)m);
+      }
+    } else {
+      static_assert(P == P64 || P == P32, "FP16 is packed from the FP64 matrices (k_pack_f16_from_f64)");
       float4* o = reinterpret_cast<float4*>(base) + lane;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         if (j < (two_rows ? 3 : 4))
           o[j * kWave] = make_float4((float)u[2 * j].x, (float)u[2 * j].y, (float)u[2 * j + 1].x, (float)u[2 * j + 1].y);
       if (!two_rows) reinterpret_cast<float2*>(base + 4 * kWave * 16)[lane] = make_float2((float)u[8].x, (float)u[8].y);
-    } else {
-      const float sc = scale[(k >> 1) & 1];
-      h2v h[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        h[e].x = f16_code(u[e].x, sc);
-        h[e].y = f16_code(u[e].y, sc);
-      }
-      uint4* o = reinterpret_cast<uint4*>(base) + lane;
-      if (two_rows) {
-        o[0] = make_uint4(__builtin_bit_cast(unsigned, h[0]), __builtin_bit_cast(unsigned, h[1]),
-                          __builtin_bit_cast(unsigned, h[2]), __builtin_bit_cast(unsigned, h[3]));
-        reinterpret_cast<uint2*>(base + kWave * 16)[lane] =
-            make_uint2(__builtin_bit_cast(unsigned, h[4]), __builtin_bit_cast(unsigned, h[5]));
-      } else {
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          o[j * kWave] = make_uint4(__builtin_bit_cast(unsigned, h[4 * j]), __builtin_bit_cast(unsigned, h[4 * j + 1]),
-                                    __builtin_bit_cast(unsigned, h[4 * j + 2]), __builtin_bit_cast(unsigned, h[4 * j + 3]));
-        reinterpret_cast<unsigned*>(base + 2 * kWave * 16)[lane] = __builtin_bit_cast(unsigned, h[8]);
-      }
     }
   }
+  if (scales64) {
+    lscale[blk * 2 * kWave + lane] = scale[0];
+    lscale[blk * 2 * kWave + kWave + lane] = scale[1];
+  }
+}
+
+// FP16 packing from the FP64 packed matrices and the scales the FP64 pack computed (when both are
+// requested): one coalesced pass over the packed FP64 blocks instead of folding every link again from
+// the input fields twice (once for the scales, once for the codes).  The codes are the same, since the
+// FP64 packed entries are the folded matrices themselves.
+__global__ __launch_bounds__(256) void k_pack_f16_from_f64(const char* packed64, const float* lscale, int half,
+                                                          int c12, char* out) {
+  const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+  const int padded = ceil_div(half, kWave) * kWave;
+  if (cb >= padded) return;
+  const long blk = cb >> 6;
+  const int lane = cb & 63;
+  const float scale[2] = {lscale[blk * 2 * kWave + lane], lscale[blk * 2 * kWave + kWave + lane]};
+  for (int k = 0; k < kLinks; ++k) {
+    const bool two_rows = c12 && ((k & 3) >= 2);
+    const double2* in = reinterpret_cast<const double2*>(packed64 + link_slot_offset(P64, c12, blk, k)) + lane;
+    double2 u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = e < (two_rows ? 6 : 9) ? in[e * kWave] : make_double2(0.0, 0.0);
+    const float sc = scale[(k >> 1) & 1];
+    h2v h[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      h[e].x = f16_code(u[e].x, sc);
+      h[e].y = f16_code(u[e].y, sc);
+    }
+    char* base = out + link_slot_offset(P16, c12, blk, k);
+    uint4* o = reinterpret_cast<uint4*>(base) + lane;
+    if (two_rows) {
+      o[0] = make_uint4(__builtin_bit_cast(unsigned, h[0]), __builtin_bit_cast(unsigned, h[1]),
+                        __builtin_bit_cast(unsigned, h[2]), __builtin_bit_cast(unsigned, h[3]));
+      reinterpret_cast<uint2*>(base + kWave * 16)[lane] =
+          make_uint2(__builtin_bit_cast(unsigned, h[4]), __builtin_bit_cast(unsigned, h[5]));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        o[j * kWave] = make_uint4(__builtin_bit_cast(unsigned, h[4 * j]), __builtin_bit_cast(unsigned, h[4 * j + 1]),
+                                  __builtin_bit_cast(unsigned, h[4 * j + 2]), __builtin_bit_cast(unsigned, h[4 * j + 3]));
+      reinterpret_cast<unsigned*>(base + 2 * kWave * 16)[lane] = __builtin_bit_cast(unsigned, h[8]);
+    }
+  }
+}
+
+hipError_t launch_pack_f16_from_f64(const void* packed64, const float* lscale, const Geo& g, void* out,
+                                    hipStream_t st) {
+  const int padded = ceil_div(g.half, kWave) * kWave;
+  k_pack_f16_from_f64<<<ceil_div(padded, 256), 256, 0, st>>>(reinterpret_cast<const char*>(packed64), lscale, g.half,
+                                                             g.long12, reinterpret_cast<char*>(out));
+  return hipGetLastError();
 }
 
 hipError_t launch_pack_links(int prec, const void* fat, const void* lng, double naik, const Geo& g, int antiper,
@@ -158,7 +188,6 @@ hipError_t launch_pack_links(int prec, const void* fat, const void* lng, double 
   switch (prec) {
     case P64: k_pack_links<P64><<<nblk, 256, 0, st>>>(f, l, naik, g, antiper, par, o, lscale); break;
     case P32: k_pack_links<P32><<<nblk, 256, 0, st>>>(f, l, naik, g, antiper, par, o, lscale); break;
-    case P16: k_pack_links<P16><<<nblk, 256, 0, st>>>(f, l, naik, g, antiper, par, o, lscale); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
