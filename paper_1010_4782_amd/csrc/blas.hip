@@ -292,23 +292,30 @@ __global__ __launch_bounds__(kMaxWG) void k_fcg_beta_dot(Batch B, int gate) {
 }
 
 // One workgroup per slot: sum the partials of `kind` in a fixed order and apply `what`.  The
-// partials (about 2^14 per slot on the largest lattices) come from HBM after the producing
-// launch, so the sum is latency-bound: 16 waves issue all their loads (up to 16 per lane) before
-// the first add, which takes one memory round trip instead of one per load.
+// partials (about 2^14 per slot for a 28^3x96 Dslash of 64-site workgroups) come from HBM after the
+// producing launch, so the kernel is a chain of memory round trips.  It is kept short: the problem
+// size and the slot scalars that the per-iteration alpha and beta steps read are requested together
+// at the start, and 16 waves issue all their loads (up to 24 per lane, one pass up to 24576
+// partials) before the first add.  Lane t adds the partials t, t + 1024, t + 2048, ... in that order
+// whatever the number of passes, so the sum does not depend on the unroll depth.
 constexpr int kFinWG = 1024;
-constexpr int kFinUnroll = 16;
+constexpr int kFinUnroll = 24;
 __global__ __launch_bounds__(kFinWG) void k_finalize(Batch B, int what, int kind, int gate, int producer_wg,
                                                      int aux_wg, double* hist, int hist_stride) {
   __shared__ double lds[3 * (kFinWG / kWave)];
   const int slot = blockIdx.x;
   int p = 0;
   while (p + 1 < B.nprob && slot >= B.probs[p + 1].slot0) ++p;
+  const Scal& pre = B.scal[slot];
+  const int st = pre.state, iter0 = pre.iter, max_iter0 = pre.max_iter;
+  const double delta0 = pre.delta, thr0 = pre.thr, rel_thr0 = pre.rel_thr;
+  const int half = B.probs[p].g.half;
   if (!slot_on(B.scal, slot, gate)) return;
   const int nk = (what == FIN_ORTHO || what == FIN_FCG_ALPHA) ? 3 : (what == FIN_FCG_BETA ? 2 : 1);
   double s[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < nk; ++k) {
     // the first kind comes from a launch of producer_wg sites per block, the others from aux_wg
-    const int ntiles = ceil_div(B.probs[p].g.half, k == 0 ? producer_wg : aux_wg);
+    const int ntiles = ceil_div(half, k == 0 ? producer_wg : aux_wg);
     const double* src = B.partial + ((long)slot * kPartialSlots + kind + k) * B.pstride;
     double v[kFinUnroll];
     for (int base = 0; base < ntiles; base += kFinUnroll * kFinWG) {
@@ -341,43 +348,47 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(Batch B, int what, int kind
         sc.state = sum <= sc.thr ? 2 : 0;
       }
       break;
-    case FIN_ALPHA:
-      if (sc.state == 1) {
+    case FIN_ALPHA: {
+      if (st == 1) {
         sc.state = 2;
         break;
       }
-      if (sc.state != 0) break;
+      if (st != 0) break;
       sc.dAd = sum;
       if (!(sum > 0.0) || !isfinite(sum)) {
         sc.flags |= kFlagNaN;
         sc.state = 2;
         break;
       }
-      sc.alpha = sc.delta / sum;
-      if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2] = sc.alpha;
+      const double alpha = delta0 / sum;
+      sc.alpha = alpha;
+      if (hist && iter0 < sc.hist_len) hist[((long)slot * hist_stride + iter0) * 2] = alpha;
       break;
-    case FIN_BETA:
-      if (sc.state != 0) break;
+    }
+    case FIN_BETA: {
+      if (st != 0) break;
       if (!isfinite(sum)) {
         sc.flags |= kFlagNaN;
         sc.state = 2;
         break;
       }
-      sc.delta_old = sc.delta;
+      const double beta = sum / delta0;
+      sc.delta_old = delta0;
       sc.delta = sum;
-      sc.beta = sum / sc.delta_old;
-      if (hist && sc.iter < sc.hist_len) hist[((long)slot * hist_stride + sc.iter) * 2 + 1] = sc.beta;
-      sc.iter += 1;
-      if (sum <= sc.thr) sc.state = 1;
-      if (sum <= sc.rel_thr) {
+      sc.beta = beta;
+      if (hist && iter0 < sc.hist_len) hist[((long)slot * hist_stride + iter0) * 2 + 1] = beta;
+      sc.iter = iter0 + 1;
+      if (sum <= thr0) sc.state = 1;
+      if (sum <= rel_thr0) {
         sc.state = 1;
         sc.flags |= kFlagRelDue;
       }
-      if (sc.iter >= sc.max_iter) {
+      if (iter0 + 1 >= max_iter0) {
         sc.state = 1;
         sc.flags |= kFlagMaxIter;
       }
       break;
+    }
     case FIN_TRUE:
       sc.aux = sqrt(sum / sc.b2);
       sc.delta = sum;
