@@ -134,6 +134,39 @@ def test_cg_f64_matches_oracle_iterates(gpu_lib):
     np.testing.assert_allclose(hist[0, :, 1], ref.betas, rtol=1e-10)
 
 
+def test_cg_first_step_scalars_many_partials(gpu_lib):
+    """36^3 x 72 with 64-site operator workgroups: <d, Ad> arrives as 26,244 partials, more than the
+    24,576 one pass of the device-side finalize sums, so the second (ragged) pass is exercised.
+    alpha_0 = |b|^2 / <b, M b> and beta_0 = |b - alpha_0 M b|^2 / |b|^2 (Fig. 1 with x0 = 0) from
+    the oracle's own M.  The links are complex Gaussian matrices (any links keep D_eo = -D_oe^dagger,
+    so M stays Hermitian positive definite), cheaper to draw at this size than SU(3) fields."""
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    dims = (36, 36, 36, 72)
+    print(f"cg first-step scalars {dims}", flush=True)
+    rng = np.random.default_rng(3601)
+    shp = (4, dims[3], dims[2], dims[1], dims[0], 3, 3)
+    fat = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) * 0.4
+    lng = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) * 0.4
+    b = gaussian_source(dims, 3610)[0]
+    m = 0.0062
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK)
+    lat.set_dslash_shape("f64", 1, 64, 1)
+    assert -(-len(b) // 64) > 24576
+    hist = np.zeros((1, 2, 2))
+    _, info = lat.cg_solve(torch.from_numpy(b).cuda(), m, max_iter=2, max_restarts=0, history_len=2,
+                           history=hist, raise_on_fail=False)
+    assert info[0]["iters"] == 2
+    Mb = apply_m(fat, lng, b, dims, m)
+    b2 = np.vdot(b, b).real
+    alpha0 = b2 / np.vdot(b, Mb).real
+    r1 = b - alpha0 * Mb
+    beta0 = np.vdot(r1, r1).real / b2
+    np.testing.assert_allclose(hist[0, 0], [alpha0, beta0], rtol=1e-11)
+    lat.set_dslash_shape("f64", 1, 0, 1)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_cg_mixed_precision_true_residual(gpu_lib, prec):
     dims = (8, 8, 8, 8)
