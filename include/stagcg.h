@@ -154,7 +154,8 @@ stag_status stag_destroy_lattice(stag_lattice_t lat);
 stag_status stag_lattice_info(stag_lattice_t lat, int32_t dims[4], int64_t* half_volume);
 
 /* Fold the phases, boundary signs and c_N into the links and repack them (Sec. 2,
- * "the phase factor is multiplied to the gauge link"; Sec. 3.1 coalesced layout).
+ * Eq. (5): the staggered phases are absorbed into the stored links; Sec. 3.1
+ * coalesced layout).
  * fat, lng: device complex128 link fields (layout above); lng = NULL drops the
  * three-hop term, leaving the paper's one-hop Eq. (5).  naik_coeff: c_N (-1/24
  * for the improved action).  prec_mask: STAG_PREC_BIT of every storage precision

@@ -21,7 +21,9 @@ Staggered Fermions", Lattice 2010):
   * lowprec   - the operator applied in FP64 to inputs rounded as the storage formats round them
   * cost      - bytes and flops per site (Sec. 2 accounting)
   * net       - the gauge-covariant linear network used as a preconditioner
+  * fatten    - fat (one-hop) and long (three-hop) links built from a thin gauge
+                field by explicit path products (the published asqtad recipe)
 
 Readings of the paper where it is silent are stated in each function.
 """
-from . import geometry, dslash, dense, free, cg, fcg, quant, cost, lowprec, net  # noqa: F401
+from . import geometry, dslash, dense, free, cg, fcg, quant, cost, lowprec, net, fatten  # noqa: F401

@@ -1,7 +1,7 @@
 // Link ingest and packing, and colour-vector precision conversions.
 //
-// Packing folds into each of the 16 matrices an output site uses (Sec. 2: the
-// phase factor is multiplied into the link beforehand):
+// Packing folds into each of the 16 matrices an output site uses (Sec. 2, Eq. (5):
+// the staggered phases are absorbed into the stored links):
 //   k = 4 mu + 0 : eta_mu(n) s(n,1) F_mu(n)                       (neighbour n + mu)
 //   k = 4 mu + 1 : -eta_mu(n) s(n-mu,1) F_mu(n-mu)^dag            (neighbour n - mu)
 //   k = 4 mu + 2 : c_N eta_mu(n) s(n,3) W_mu(n)                   (neighbour n + 3mu)
