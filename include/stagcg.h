@@ -201,6 +201,16 @@ stag_status stag_dslash_slab(stag_lattice_t lat, int32_t out_parity, int32_t t0,
 stag_status stag_slice_norm2(stag_lattice_t lat, const void* v, int32_t nrhs, int32_t group, double weight,
                              int32_t accumulate, double* out, void* stream);
 
+/* The pion correlator of nsrc point-source propagators in one call: chi holds the even-site solutions
+ * of the three source colours of each source (3 nsrc consecutive right-hand sides, as for
+ * stag_slice_norm2); the library forms G_o = -D_oe chi with its FP64 Dslash and writes
+ *   out[s][t] = 4 m^2 sum_{c, slice t} |chi_(3s+c)|^2 + sum_{c, slice t} |(D_oe chi_(3s+c))|^2.
+ * chi: device complex128 [3 nsrc][V/2][3]; out: device double [nsrc][Lt]; mass: the solve's m.
+ * Asynchronous on `stream`; the odd-parity temporary is lattice workspace (grown on demand).
+ * NULL pointers, nsrc < 1 or a non-finite mass: STAG_ERR_ARG. */
+stag_status stag_pion_correlator(stag_lattice_t lat, const void* chi, int32_t nsrc, double mass, double* out,
+                                 void* stream);
+
 /* out = M in = 4 m^2 in - D_eo D_oe in on even sites (Eq. (3)), FP64.
  * mass: host double[nrhs]; in, out: device complex128 [nrhs][V/2][3], not overlapping. */
 stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,

@@ -88,3 +88,10 @@ def true_residual(apply_a, b: np.ndarray, x: np.ndarray) -> float:
     """||b - A x|| / ||b||."""
     r = b - apply_a(x)
     return float(np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real))
+
+
+def true_residuals(apply_a, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """||b_r - A x_r|| / ||b_r|| for every right-hand side r of b, x: [nrhs][...] (A applied to all at once)."""
+    r = b - apply_a(x)
+    axes = tuple(range(1, b.ndim))
+    return np.sqrt(np.sum(np.abs(r) ** 2, axis=axes) / np.sum(np.abs(b) ** 2, axis=axes))

@@ -80,7 +80,8 @@ def dslash_at_sites(fat, lng, chi_half: np.ndarray, dims, out_parity: int, cbs,
     """(D_{p,1-p} chi)(n) evaluated one output site at a time, for the sites cbs of parity p.
 
     Reads only the links and input components each site needs, so it works on
-    lattices too big for dslash_full.  Returns [len(cbs)][3].
+    lattices too big for dslash_full.  chi_half is [V/2][3] or [nrhs][V/2][3];
+    returns [len(cbs)][3] or [nrhs][len(cbs)][3].
     """
     Lx, Ly, Lz, Lt = dims
     L = np.array(dims)
@@ -93,10 +94,11 @@ def dslash_at_sites(fat, lng, chi_half: np.ndarray, dims, out_parity: int, cbs,
     t = rest // Lz
     x = 2 * xh + ((y + z + t + out_parity) % 2)
     n = np.stack([x, y, z, t], axis=1)               # [S][4]
+    multi = chi_half.ndim == 3
 
-    def chi_at(m):                                   # m: [S][4], parity 1-p
+    def chi_at(m):                                   # m: [S][4], parity 1-p -> [S][3] or [nrhs][S][3]
         lex = m[:, 0] + Lx * (m[:, 1] + Ly * (m[:, 2] + Lz * m[:, 3]))
-        return chi_half[lex // 2]
+        return chi_half[:, lex // 2] if multi else chi_half[lex // 2]
 
     def link(U, mu, m):
         return U[mu, m[:, 3], m[:, 2], m[:, 1], m[:, 0]]
@@ -106,7 +108,7 @@ def dslash_at_sites(fat, lng, chi_half: np.ndarray, dims, out_parity: int, cbs,
             return np.ones(len(m))
         return np.where(((m[:, 3] + k) // Lt) % 2 == 0, 1.0, -1.0)
 
-    out = np.zeros((len(cbs), 3), dtype=np.complex128)
+    out = np.zeros(chi_half.shape[:-2] + (len(cbs), 3), dtype=np.complex128)
     terms = [(1, fat, 1.0)]
     if lng is not None and naik != 0.0:
         terms.append((3, lng, naik))
@@ -121,6 +123,44 @@ def dslash_at_sites(fat, lng, chi_half: np.ndarray, dims, out_parity: int, cbs,
             term -= sign(mu, k, bwd)[:, None] * _dagger_matvec(link(U, mu, bwd), chi_at(bwd))
             out += c * e[:, None] * term
     return out
+
+
+def dslash_eo_chunked(fat, lng, chi_half: np.ndarray, dims, out_parity: int, chunk: int = 1 << 16,
+                      workers: int = 1, antiperiodic_t: bool = True, naik: float = NAIK_COEFF) -> np.ndarray:
+    """D_{p,1-p} on every output site, computed by dslash_at_sites over consecutive chunks of sites.
+
+    The same definition as dslash_eo with memory bounded by the chunk; chunks are independent, so
+    `workers` threads may evaluate them concurrently (NumPy's gathers and products release the GIL).
+    chi_half is [V/2][3] or [nrhs][V/2][3].
+    """
+    from concurrent.futures import ThreadPoolExecutor
+
+    half = chi_half.shape[-2]
+    out = np.empty(chi_half.shape, dtype=np.complex128)
+
+    def run(c0):
+        cbs = np.arange(c0, min(half, c0 + chunk))
+        out[..., c0:c0 + len(cbs), :] = dslash_at_sites(fat, lng, chi_half, dims, out_parity, cbs,
+                                                        antiperiodic_t, naik)
+
+    starts = range(0, half, chunk)
+    if workers <= 1:
+        for c0 in starts:
+            run(c0)
+    else:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(run, starts))
+    return out
+
+
+def apply_m_chunked(fat, lng, chi_e: np.ndarray, dims, mass, chunk: int = 1 << 16, workers: int = 1,
+                    antiperiodic_t: bool = True, naik: float = NAIK_COEFF) -> np.ndarray:
+    """M chi_e = 4 m^2 chi_e - D_eo D_oe chi_e with the chunked operator; chi_e [V/2][3] or [nrhs][V/2][3],
+    mass a scalar or one per right-hand side."""
+    t_o = dslash_eo_chunked(fat, lng, chi_e, dims, 1, chunk, workers, antiperiodic_t, naik)
+    m = np.asarray(mass, dtype=np.float64)
+    m4 = (4.0 * m * m).reshape(m.shape + (1, 1)) if m.ndim else 4.0 * m * m
+    return m4 * chi_e - dslash_eo_chunked(fat, lng, t_o, dims, 0, chunk, workers, antiperiodic_t, naik)
 
 
 def gauge_transform_links(fat, lng, g, dims):
@@ -150,5 +190,6 @@ def colour_rotate(g, chi):
     return _matvec(g, chi)
 
 
-__all__ = ["dslash_full", "dslash_eo", "apply_m", "dslash_at_sites", "gauge_transform_links",
+__all__ = ["dslash_full", "dslash_eo", "apply_m", "dslash_at_sites", "dslash_eo_chunked", "apply_m_chunked",
+           "gauge_transform_links",
            "pure_gauge_links", "colour_rotate", "coords", "NAIK_COEFF"]

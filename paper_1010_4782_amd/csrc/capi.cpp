@@ -445,6 +445,36 @@ stag_status stag_slice_norm2(stag_lattice_t lat, const void* v, int32_t nrhs, in
   STAG_GUARD_END
 }
 
+stag_status stag_pion_correlator(stag_lattice_t lat, const void* chi, int32_t nsrc, double mass, double* out,
+                                 void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (!chi || !out) return arg_error("chi and out must not be NULL");
+  if (nsrc < 1) return arg_error("nsrc must be >= 1");
+  if (!std::isfinite(mass)) return arg_error("mass must be finite");
+  const int nrhs = 3 * nsrc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  STAG_HIP_TRY(lat->vec[V_TMPO].ensure(spinor_field_bytes(lat, P64, nrhs)));
+  void* ov[kNumVec] = {};
+  ov[V_D] = const_cast<void*>(chi);
+  BatchHost bh;
+  RingEntry e;
+  s = single_batch(lat, nrhs, nullptr, ov, st, bh, e);
+  if (s != STAG_OK) return s;
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, P64), P64);
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh, st));
+  s = ring_release(lat->ctl, e, st);
+  if (s != STAG_OK) return s;
+  const int lt = lat->dims[3];
+  const long half = lat->g.half;
+  // |D_oe chi|^2 = |G_o|^2 (the sign of G_o does not enter); the even part carries (2m)^2
+  STAG_HIP_TRY(launch_slice_norm2(chi, half, half / lt, lt, nsrc, 3, 4.0 * mass * mass, 0, out, st));
+  STAG_HIP_TRY(launch_slice_norm2(lat->vec[V_TMPO].ptr, half, half / lt, lt, nsrc, 3, 1.0, 1, out, st));
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
 stag_status stag_cg_solve(stag_lattice_t lat, const double* mass, const void* b, void* x, int32_t nrhs,
                           const stag_cg_params* prm, stag_cg_info* info, void* stream) {
   STAG_GUARD_BEGIN

@@ -163,15 +163,21 @@ class Lattice:
                                      out.data_ptr(), _stream(stream)), "stag_slice_norm2")
         return out
 
-    def pion_correlator(self, chi: torch.Tensor, mass: float, stream=None) -> torch.Tensor:
+    def pion_correlator(self, chi: torch.Tensor, mass: float, out=None, stream=None) -> torch.Tensor:
         """C[s][t] of point-source propagators from their even-site solutions chi (3 consecutive RHS, the
-        source colours, per source): G_e = 2m chi and G_o = -D_oe chi, C(t) = sum over slice t of |G|^2."""
+        source colours, per source), computed by stag_pion_correlator."""
         nrhs = self._vec(chi, "chi")
         if nrhs % 3:
             raise ValueError("chi holds three right-hand sides (source colours) per source")
-        odd = self.dslash(chi, 1, stream=stream)
-        C = self.slice_norm2(chi, 3, 4.0 * mass * mass, stream=stream)
-        return self.slice_norm2(odd, 3, 1.0, out=C, accumulate=True, stream=stream)
+        nsrc = nrhs // 3
+        if out is None:
+            out = torch.empty((nsrc, self.dims[3]), dtype=torch.float64, device=chi.device)
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or \
+                tuple(out.shape) != (nsrc, self.dims[3]):
+            raise ValueError(f"out must be a contiguous float64 CUDA tensor of shape {(nsrc, self.dims[3])}")
+        check(lib().stag_pion_correlator(self._h, chi.data_ptr(), nsrc, float(mass), out.data_ptr(),
+                                         _stream(stream)), "stag_pion_correlator")
+        return out
 
     def apply_m(self, x: torch.Tensor, mass, out=None, stream=None) -> torch.Tensor:
         nrhs = self._vec(x, "in")

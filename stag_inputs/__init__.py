@@ -23,6 +23,10 @@ not available here):
   * sources: real and imaginary parts N(0,1) per colour component.
   * Generator: numpy PCG64 default_rng(seed).  Seeds for workload i (1-based):
     fat = 1000 i + 1, long = 1000 i + 2, source j = 1000 i + 10 + j.
+  * The 48^3x144 link fields (two fields of 63.7M matrices, minutes on the host)
+    follow the same recipe but are drawn on the GPU with a seeded torch generator
+    (`random_su3_field_device`, `fat_field_device`, `workload_links_device`); the
+    oracle reads host copies of those very tensors.
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ __all__ = [
     "GELL_MANN", "WORKLOADS", "su3_near_identity", "random_su3_field",
     "fat_field", "gaussian_source", "gaussian_source_device", "gaussian_full_field", "random_gauge_transform",
     "workload", "workload_links", "workload_sources", "point_sources", "half_volume", "volume",
+    "random_su3_field_device", "fat_field_device", "workload_links_device", "DEVICE_LINK_WORKLOADS",
 ]
 
 
@@ -164,6 +169,66 @@ def random_gauge_transform(dims, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     g = su3_near_identity(rng, Lt * Lz * Ly * Lx, eps=1.0)
     return g.reshape(Lt, Lz, Ly, Lx, 3, 3)
+
+
+def random_su3_field_device(dims, seed: int, eps: float = 0.3, device="cuda"):
+    """The su3(eps) recipe of random_su3_field drawn on the GPU: a complex128 torch tensor
+    [4][Lt][Lz][Ly][Lx][3][3] from a torch generator seeded with `seed`, eight time slices at a time.
+    Deterministic for a given seed, device type and torch version (not the host stream)."""
+    import torch
+
+    Lx, Ly, Lz, Lt = _check_dims(dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    lam = torch.from_numpy(GELL_MANN.reshape(8, 9)).to(device)
+    out = torch.empty((4, Lt, Lz, Ly, Lx, 3, 3), dtype=torch.complex128, device=device)
+    slab = Lz * Ly * Lx
+    for mu in range(4):
+        for t0 in range(0, Lt, 8):
+            n = min(8, Lt - t0)
+            h = torch.randn((n * slab, 8), generator=g, dtype=torch.float64, device=device)
+            H = (h.to(torch.complex128) @ lam).reshape(n * slab, 3, 3) * 0.5
+            out[mu, t0:t0 + n] = torch.linalg.matrix_exp(1j * eps * H).reshape(n, Lz, Ly, Lx, 3, 3)
+    return out
+
+
+def fat_field_device(dims, seed: int, scale: float = 0.6, sigma: float = 0.05, device="cuda"):
+    """fat_field's recipe on the GPU: scale * su3(0.3) + sigma * (N + iN) per entry, the noise from a
+    second generator seeded with 1000003 * seed + 1."""
+    import torch
+
+    U = random_su3_field_device(dims, seed, device=device)
+    U *= scale
+    g = torch.Generator(device=device)
+    g.manual_seed(1000003 * int(seed) + 1)
+    for mu in range(4):
+        for t in range(U.shape[1]):
+            shp = U[mu, t].shape
+            re = torch.randn(shp, generator=g, dtype=torch.float64, device=device)
+            im = torch.randn(shp, generator=g, dtype=torch.float64, device=device)
+            U[mu, t] += sigma * torch.complex(re, im)
+    return U
+
+
+# workloads whose link fields are drawn on the GPU (their host generation takes minutes)
+DEVICE_LINK_WORKLOADS = (5,)
+
+
+def workload_links_device(i: int, lattice_index: int = 0, device="cuda"):
+    """(fat, long) of workload i as torch tensors on the GPU: drawn there for the workloads in
+    DEVICE_LINK_WORKLOADS, otherwise the host fields of workload_links copied over."""
+    import torch
+
+    w = WORKLOADS[i]
+    if i not in DEVICE_LINK_WORKLOADS:
+        fat, lng = workload_links(i, lattice_index)
+        return torch.from_numpy(fat).to(device), torch.from_numpy(lng).to(device)
+    dims = w["lattices"][lattice_index][0]
+    seed_f = 1000 * i + 1 + 100 * lattice_index
+    seed_l = 1000 * i + 2 + 100 * lattice_index
+    fat = random_su3_field_device(dims, seed_f, device=device) if w["fat"] == "unitary" else \
+        fat_field_device(dims, seed_f, device=device)
+    return fat, random_su3_field_device(dims, seed_l, device=device)
 
 
 def workload(i: int) -> dict:

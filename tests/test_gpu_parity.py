@@ -323,37 +323,6 @@ def test_dslash_full_size_28cubed_96_sampled(gpu_lib, long_su3):
         assert rel(out[sample], ref) <= 1e-12
 
 
-def test_dslash_full_size_48cubed_144_eight_rhs_sampled(gpu_lib):
-    """The largest single-GPU workload, 48^3 x 144 with 8 right-hand sides, in the launch shape its
-    benchmark runs (8 right-hand sides per lane, 12-real long links): sampled sites of every RHS vs
-    the oracle, both output parities."""
-    from paper_1010_4782_amd.stagcg import Lattice
-    from stag_inputs import WORKLOADS, workload_links, workload_sources
-
-    dims, nrhs = WORKLOADS[5]["lattices"][0]
-    print(f"dslash {dims} x {nrhs} RHS sampled (input generation takes about a minute)", flush=True)
-    fat, lng = workload_links(5)
-    b = workload_sources(5)
-    lat = Lattice(dims)
-    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64",), long_su3=True)
-    lat.set_dslash_shape("f64", nrhs, 64, 8)
-    bt = torch.from_numpy(b).cuda()
-    half = b.shape[1]
-    rng = np.random.default_rng(5)
-    sample = np.concatenate([rng.integers(0, half, 96), np.arange(32), np.arange(half - 32, half)])
-    for par in (0, 1):
-        out = lat.dslash(bt, par).cpu().numpy()
-        for r in range(nrhs):
-            ref = dslash_at_sites(fat, lng, b[r], dims, par, sample)
-            assert rel(out[r][sample], ref) <= 1e-12, (par, r)
-    # the LDS-staged shape and the XCD-block tile order at full size give the same bits
-    lat.set_dslash_shape("f64", nrhs, 64, 4, 1)
-    assert np.array_equal(lat.dslash(bt, 1).cpu().numpy(), out)
-    lat.set_dslash_shape("f64", nrhs, 64, 4, 0, 1)
-    assert np.array_equal(lat.dslash(bt, 1).cpu().numpy(), out)
-    lat.set_dslash_shape("f64", nrhs, 0, 1)
-
-
 def test_dslash_identical_for_every_launch_shape(gpu_lib):
     """Workgroup size, right-hand sides per lane and LDS staging change the schedule, not the arithmetic:
     bitwise equal."""
@@ -516,32 +485,6 @@ def test_batch_rejects_mixed_long_link_storage(gpu_lib):
     b = torch.from_numpy(gaussian_source(dims, 125)).cuda()
     with pytest.raises(StagError):
         cg_solve_batch([(lat_a, b, [0.1], None), (lat_b, b, [0.1], None)], tol=1e-10)
-
-
-def test_batched_full_size_uneven_lattices(gpu_lib):
-    """The batched workload at full size: 16^4 x 4 + 24^3x48 x 12 + 32^3x64 x 8 right-hand sides in one
-    batch (mass 0.01, the hardest of its three), mixed precision with the autotuner, 12-real links.
-    Every RHS must report convergence; the first RHS of each lattice is re-checked by the oracle."""
-    from paper_1010_4782_amd.stagcg import Lattice, cg_solve_batch
-    from stag_inputs import WORKLOADS, workload_links, workload_sources
-
-    w = WORKLOADS[3]
-    mass = w["masses"][0]
-    print("batched full size (input generation and oracle checks take about a minute)", flush=True)
-    probs, hosts = [], []
-    for li, (dims, nrhs) in enumerate(w["lattices"]):
-        fat, lng = workload_links(3, li)
-        b = workload_sources(3, li)
-        lat = Lattice(dims)
-        lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"),
-                       long_su3=True)
-        probs.append((lat, torch.from_numpy(b).cuda(), [mass] * nrhs, None))
-        hosts.append((fat, lng, dims, b))
-    xs, infos = cg_solve_batch(probs, tol=w["tol"], prec="f16", autotune=True)
-    assert all(i["converged"] == 1 and i["true_resid"] <= w["tol"] for i in infos)
-    for (fat, lng, dims, b), x in zip(hosts, xs):
-        x0 = x[0].cpu().numpy()
-        assert true_residual(lambda v: apply_m(fat, lng, v, dims, mass), b[0], x0) <= 1.05 * w["tol"]
 
 
 @pytest.mark.parametrize("prec,long_su3", [("f64", False), ("f64", True), ("f16", True)])
