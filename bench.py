@@ -1,15 +1,25 @@
-"""Benchmark: time to a 1e-10 true residual on 28^3 x 96, mixed precision vs plain FP64 CG, plus Dslash GB/s.
+"""Benchmark: time to a 1e-10 true residual, mixed precision vs plain FP64 CG, and Dslash HBM GB/s.
 
-    python bench.py [--steps K] [--warmup W] [--workload 2] [--prec f16] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload 5] [--prec f16] [--no-cpu-baseline]
 
-A step is one pass of the whole hot path over the workload's synthetic input,
-which is resident in HBM before timing starts: pack the links (phases, signs and
-c_N folded; FP64 + the inner precision) and solve (4m^2 - D_eo D_oe) x = b with
-mixed-precision CG and FP64 reliable updates to true residual 1e-10.  The plain
-FP64 CG solve of the same system is timed once beside it.  The two Dslash launches
-of every 10th CG iteration of the timed steps are bracketed by HIP events on the
-solver's stream; their average duration gives the roofline figure.  Prints one JSON
-line.
+The default line is the largest single-GPU workload: a 48^3x144 lattice with 8 right-hand sides,
+m = 0.0062, solved to true residual 1e-10.  A step is one pass of the whole hot path over the
+workload's synthetic input, which is resident in HBM before timing starts: pack the links (phases,
+boundary signs and c_N folded; FP64 + FP16) and solve (4m^2 - D_eo D_oe) x = b for all 8 right-hand
+sides with mixed-precision CG (FP16 storage, FP32 arithmetic, FP64 reliable updates), 8 right-hand
+sides per Dslash launch.  The two Dslash launches of every 10th iteration are bracketed by HIP events
+on the solver's stream; their average duration gives the roofline figure.
+
+Beside the timed steps the line carries, each with its own timing:
+  * the plain FP64 CG of the same system (warm-up, then timed solves);
+  * `paper_lattice`: the 28^3x96 single-RHS record (FP16 and FP32 mixed precision, FP64 CG);
+  * `with_network`: the same 8-RHS solve with the learned preconditioner in flexible CG (the network
+    trained on 24^3x48 pairs and applied on the large lattice);
+  * `stream_ceiling`: a read-only streaming kernel of the library on this GPU;
+  * `cpu_baseline`: the oracle on the host, one thread and all threads, extrapolated from a bounded
+    sample of the same workload;
+  * `leg_seconds`: the wall time of every leg.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -44,6 +54,12 @@ def dslash_bytes_per_site(prec: str, xpay: bool = False, long12: bool = True) ->
     return link_bytes_per_site(prec, long12) + 2 * VEC[prec] + (VEC[prec] if xpay else 0)
 
 
+def launch_bytes(prec: str, half: int, nrhs: int, long12: bool = True) -> float:
+    """Compulsory bytes of one Dslash launch of the solver, the plain and the xpay launch averaged:
+    each link once, every RHS's input and output vectors, half a vector more for the xpay read of d."""
+    return half * (link_bytes_per_site(prec, long12) + nrhs * 2.5 * VEC[prec])
+
+
 def host_info():
     model = ""
     try:
@@ -56,51 +72,80 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu_model": model or platform.processor()}
 
 
-def cpu_baseline(fat, lng, b, dims, mass, iters_fp64):
-    """The oracle's CG as it stands, on one core, for a bounded sample: one Fig. 1 iteration
-    (plus the initial and final residual) on the full lattice, scaled to a whole solve."""
-    import numpy as np
+def cpu_workers() -> int:
+    """Threads for the oracle's threaded mode: the cores this process may run on (at most 16, the CPU
+    share of a one-GPU machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
-    from oracle.cg import cg
-    from oracle.dslash import apply_m
 
-    # pin every BLAS / OpenMP pool numpy may use to one thread, so that "cores" is what ran
+def cpu_baseline(fat, lng, b, dims, mass, iters_fp64, nrhs=1, workers=None):
+    """The oracle as it stands on a bounded sample of the workload: one operator application
+    M = 4m^2 - D_eo D_oe on one right-hand side of the full lattice (the bulk of a CG iteration: the
+    iteration adds a few vector updates), timed with BLAS pinned to one thread (`oracle.dslash.apply_m`)
+    and, if workers > 1, with the chunked operator on that many threads (`apply_m_chunked`).  Each is
+    scaled to a whole solve: per-application time x the GPU FP64 iteration count x nrhs."""
     from threadpoolctl import threadpool_limits
+
+    from oracle.dslash import apply_m, apply_m_chunked
 
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        cg(lambda v: apply_m(fat, lng, v, dims, mass), b, tol=1e-10, max_iter=1, max_restarts=0)
-        dt = time.perf_counter() - t0
-    per_iter = dt / 3.0   # three operator applications: r = b - A x, one iteration, the true residual
-    return {"value": per_iter * iters_fp64, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle CG iteration on {dims[0]}^3x{dims[3]} ({dt:.1f} s for 3 operator "
-                      f"applications), scaled by the GPU FP64 iteration count {iters_fp64}; extrapolated",
-            "per_iteration_s": per_iter}
+        apply_m(fat, lng, b, dims, mass)
+        dt1 = time.perf_counter() - t0
+    out = {"value": dt1 * iters_fp64 * nrhs, "unit": "s", "cores": 1, "kind": "oracle",
+           "sample": f"one operator application (oracle.dslash.apply_m, 1 thread) on one RHS of "
+                     f"{'x'.join(map(str, dims))} took {dt1:.2f} s; scaled by the GPU FP64 iteration count "
+                     f"{iters_fp64} and {nrhs} RHS (extrapolated)",
+           "per_iteration_s": dt1}
+    if workers and workers > 1:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            apply_m_chunked(fat, lng, b, dims, mass, workers=workers)
+            dtn = time.perf_counter() - t0
+        out["threaded"] = {"value": dtn * iters_fp64 * nrhs, "unit": "s", "cores": workers,
+                           "per_iteration_s": dtn,
+                           "sample": f"the chunked oracle operator (apply_m_chunked) on {workers} threads, "
+                                     f"same sample and scaling"}
+    return out
 
 
-def copy_ceiling(torch, nbytes=2 << 30, reps=10):
-    """Device-to-device copy of a 2 GiB buffer: the streaming ceiling on this GPU (read + write bytes / time)."""
-    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
+def stream_ceiling(torch, nbytes=4 << 30, reps=10):
+    """Read-only streaming kernel of the library (stag_stream_read) over a 4 GiB buffer: the HBM read
+    ceiling on this GPU, with HIP events on the stream the kernel runs on."""
+    from paper_1010_4782_amd._lib import check, lib
+
+    buf = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    sink = torch.empty(nbytes // 32768, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def run():
+        check(lib().stag_stream_read(buf.data_ptr(), nbytes, sink.data_ptr(), int(s.cuda_stream)),
+              "stag_stream_read")
+
+    run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
     for _ in range(reps):
-        dst.copy_(src)
-    e.record()
+        run()
+    e1.record(s)
     torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
-    del src, dst
-    return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes,
-            "avg_launch_us": ms * 1e3}
+    ms = e0.elapsed_time(e1) / reps
+    del buf, sink
+    return {"GBps": nbytes / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "bytes_read": nbytes, "avg_launch_us": ms * 1e3, "kernel": "k_stream_read (stag_stream_read)"}
 
 
-def measured_traffic(prec: str, dims, long_su3: bool):
+def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1):
     """HBM bytes per Dslash launch from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source, this workload and this long-link storage; otherwise None."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.json")
+    tag = f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}" + (f"_{nrhs}rhs" if nrhs > 1 else "")
+    path = os.path.join(ROOT, "profiles", f"{tag}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -112,7 +157,135 @@ def measured_traffic(prec: str, dims, long_su3: bool):
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
-def run_learned_preconditioner(a, out_json):
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+class Solves:
+    """One workload's lattices, links and sources resident on the GPU, and its timed solves."""
+
+    def __init__(self, wid, a, keep_host=False):
+        import torch
+
+        from paper_1010_4782_amd.stagcg import Lattice
+        from stag_inputs import WORKLOADS, workload_links_device, workload_sources
+
+        self.w = WORKLOADS[wid]
+        self.wid = wid
+        self.a = a
+        self.tol = self.w["tol"]
+        self.rel_int = self.w.get("reliable_interval", 50)
+        self.probs, self.host = [], []
+        for li, (dims, nrhs) in enumerate(self.w["lattices"]):
+            fat, lng = workload_links_device(wid, li)
+            b = workload_sources(wid, li)
+            lat = Lattice(dims)
+            self.probs.append(dict(lat=lat, dims=dims, nrhs=nrhs, fat=fat, lng=lng, b=torch.from_numpy(b).cuda()))
+            self.host.append(b if keep_host else None)
+        torch.cuda.synchronize()
+
+    def host_links(self, li=0):
+        return self.probs[li]["fat"].cpu().numpy(), self.probs[li]["lng"].cpu().numpy()
+
+    def step(self, prec, profile=10, precs=None):
+        """load_links on every lattice, then one batched solve per mass; returns (infos, solve seconds)."""
+        import torch
+
+        from paper_1010_4782_amd.stagcg import cg_solve_batch
+
+        precs = precs or ("f64", prec)
+        for p in self.probs:
+            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=not self.a.no_long_su3)
+        torch.cuda.synchronize()  # load_links is asynchronous; keep its packing out of solve_s
+        infos, t_solve = [], 0.0
+        for m in self.w["masses"]:
+            batch = [(p["lat"], p["b"], [m] * p["nrhs"], None) for p in self.probs]
+            t0 = time.perf_counter()
+            _, inf = cg_solve_batch(batch, tol=self.tol, prec=prec, reliable_interval=self.rel_int, profile=profile,
+                                    max_iter=self.a.max_iter, max_restarts=0 if self.a.max_iter else 5,
+                                    raise_on_fail=self.a.max_iter == 0, autotune=not self.a.no_autotune)
+            t_solve += time.perf_counter() - t0  # the call synchronises before returning
+            infos.append(inf)
+        return infos, t_solve
+
+    def timed(self, prec, steps, warmup, precs=None):
+        import torch
+
+        for i in range(warmup):
+            self.step(prec, precs=precs)
+            log(f"{self.w['name']} {prec}: warmup {i} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        all_infos, solve = [], 0.0
+        for i in range(steps):
+            infos, ts = self.step(prec, precs=precs)
+            all_infos.append(infos)
+            solve += ts
+            its = [max(x["iters"] for x in inf) for inf in infos]
+            res = max(x["true_resid"] for inf in infos for x in inf)
+            log(f"{self.w['name']} {prec}: step {i}: iterations {its}, worst true resid {res:.3e}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        return all_infos, elapsed / steps, solve / steps
+
+    def dslash_rate(self, infos, prec):
+        """Algorithmic GB/s of the inner-iteration Dslash launches (plain and xpay averaged), from the
+        sampled HIP-event timings of the solves."""
+        flat = [inf for infos_ in infos for inf in infos_]
+        ms = sum(i[0]["dslash_ms"] for i in flat)
+        calls = sum(i[0]["dslash_calls"] for i in flat)
+        per_launch = sum(launch_bytes(prec, p["lat"].half, p["nrhs"], not self.a.no_long_su3) for p in self.probs)
+        avg = ms / max(calls, 1)
+        sites = sum(p["lat"].half * p["nrhs"] for p in self.probs)
+        return dict(GBps=per_launch / (avg * 1e-3) / 1e9, avg_launch_us=avg * 1e3, bytes_per_launch=per_launch,
+                    launches=calls, gflops=sites * FLOPS_PER_SITE / (avg * 1e-3) / 1e9)
+
+    def summary(self, infos):
+        last = infos[-1]
+        return {"iters": [max(x["iters"] for x in inf) for inf in last],
+                "reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
+                "true_resid": max(x["true_resid"] for inf in last for x in inf),
+                "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"],
+                                 "lds_stage": last[0][0]["dslash_lds"], "tile_order": last[0][0]["dslash_order"]}}
+
+    def shape_name(self):
+        return "+".join(f"{p['dims'][0]}^3x{p['dims'][3]}x{p['nrhs']}" if p["dims"][0] == p["dims"][2] else
+                        f"{'x'.join(map(str, p['dims']))}x{p['nrhs']}" for p in self.probs)
+
+    def close(self):
+        import torch
+
+        for p in self.probs:
+            p["lat"].close()
+        self.probs = []
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
+def solve_record(s: Solves, a, steps, warmup, fp64_steps, extra_precs=()):
+    """Mixed precision timed over the steps, plain FP64 CG over fp64_steps (after one warm-up), and any
+    further inner precisions timed like the first.  Returns (record, infos of the mixed-precision steps)."""
+    infos, per_step, solve = s.timed(a.prec, steps, warmup)
+    rate = s.dslash_rate(infos, a.prec)
+    rec = {"step_s": per_step, "solve_s": solve, **{"mp_" + k: v for k, v in s.summary(infos).items()},
+           "dslash_" + a.prec: {**rate, "frac_of_hbm_peak": rate["GBps"] / HBM_PEAK_GBPS}}
+    for prec in extra_precs:
+        inf2, step2, solve2 = s.timed(prec, steps, 1, precs=("f64", prec))
+        r2 = s.dslash_rate(inf2, prec)
+        rec["mixed_" + prec] = {"step_s": step2, "solve_s": solve2, **s.summary(inf2),
+                                "dslash": {**r2, "frac_of_hbm_peak": r2["GBps"] / HBM_PEAK_GBPS}}
+    if fp64_steps > 0:
+        i64, step64, solve64 = s.timed("f64", fp64_steps, 1, precs=("f64",))
+        r64 = s.dslash_rate(i64, "f64")
+        rec["fp64_cg"] = {"step_s": step64, "solve_s": solve64, "timed_solves": fp64_steps, **s.summary(i64),
+                          "dslash": {**r64, "frac_of_hbm_peak": r64["GBps"] / HBM_PEAK_GBPS}}
+        rec["speedup_vs_fp64_cg"] = step64 / per_step
+        rec["speedup_solve_only"] = solve64 / solve
+        log(f"{s.w['name']} fp64 CG: {rec['fp64_cg']['iters']} it, {step64:.3f} s per solve")
+    return rec, infos
+
+
+def run_learned_preconditioner(a):
     """Workload 4: train the network on (b, x = M^-1 b) pairs made by the batched FP64 solver, then time
     flexible CG with it against plain FP64 CG and mixed-precision CG on the workload's source."""
     import torch
@@ -139,21 +312,20 @@ def run_learned_preconditioner(a, out_json):
     for c0 in range(0, npairs, chunk):
         n = min(chunk, npairs - c0)
         bs[c0:c0 + n] = gaussian_source_device(dims, 4000 + c0, n)
-        x, _ = lat.cg_solve(bs[c0:c0 + n].contiguous(), mass, tol=tol, autotune=True)
+        x, _ = lat.cg_solve(bs[c0:c0 + n].contiguous(), mass, tol=tol, prec=a.prec, autotune=True)
         xs[c0:c0 + n] = x
         if (c0 // chunk) % 25 == 0:
-            print(f"# training data {c0 + n}/{npairs}", file=sys.stderr, flush=True)
+            log(f"training data {c0 + n}/{npairs}")
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Net(lat, layers=w["layers"], channels=w["channels"], seed=1, hermitian=True)
     t0 = time.perf_counter()
     tinfo = net.train(bs, xs, epochs=a.epochs, batch=8, lr=a.lr, loss=a.loss, mass=mass)
     t_train = time.perf_counter() - t0
-    print(f"# trained: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} in {t_train:.1f} s",
-          file=sys.stderr, flush=True)
+    log(f"trained: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} in {t_train:.1f} s")
     del bs, xs
     res = {}
-    for name, kw in (("fcg_net", dict(net=net, stall_window=10)), ("fp64_cg", {}),
+    for name, kw in (("fcg_net_" + a.prec, dict(net=net, stall_window=10, prec=a.prec)), ("fp64_cg", {}),
                      ("mixed_" + a.prec, dict(prec=a.prec))):
         lat.cg_solve(b_eval, mass, tol=tol, autotune=True, **kw)  # warm-up (and tuning)
         times = []
@@ -163,36 +335,38 @@ def run_learned_preconditioner(a, out_json):
             x, info = lat.cg_solve(b_eval, mass, tol=tol, **kw)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t1)
-        res[name] = {"s": min(times), "iters": info[0]["iters"], "true_resid": info[0]["true_resid"],
+        res[name] = {"s": sum(times) / len(times), "iters": info[0]["iters"], "true_resid": info[0]["true_resid"],
                      "fell_back": info[0]["fell_back"]}
-        print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+        log(f"{name}: {res[name]}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(20):
         net.apply(b_eval)
     torch.cuda.synchronize()
     t_apply = (time.perf_counter() - t1) / 20
-    out = {"metric": METRIC, "value": res["fcg_net"]["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
-           "ms_per_step": 1e3 * res["fcg_net"]["s"], "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64 (network f32)", "data": "synthetic",
+    fcg = res["fcg_net_" + a.prec]
+    out = {"metric": METRIC, "value": fcg["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
+           "ms_per_step": 1e3 * fcg["s"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 (network f32; FP64 reliable updates)", "data": "synthetic",
            "config": {"workload": f"{dims[0]}^3x{dims[3]}, m={mass}, flexible CG with a {w['layers']}-layer, "
                                   f"{w['channels']}-channel gauge-covariant network vs plain CG, true residual {tol}",
                       "train_pairs": npairs, "epochs": a.epochs, "loss": a.loss},
-           "solves": res, "speedup_fcg_vs_fp64_cg": res["fp64_cg"]["s"] / res["fcg_net"]["s"],
+           "solves": res, "speedup_fcg_vs_fp64_cg": res["fp64_cg"]["s"] / fcg["s"],
+           "speedup_fcg_vs_mixed": res["mixed_" + a.prec]["s"] / fcg["s"],
            "network_apply_ms": 1e3 * t_apply, "training": {"data_s": t_data, "train_s": t_train, **tinfo}}
-    saved = res["fp64_cg"]["s"] - res["fcg_net"]["s"]
+    saved = res["fp64_cg"]["s"] - fcg["s"]
     out["break_even_solves"] = (t_data + t_train) / saved if saved > 0 else None
     print(json.dumps(out), flush=True)
     return 0
 
 
-def network_leg(a, p, mass, tol, rel_int, mp_s, fp64_s):
-    """Workload 5's third leg: mixed precision, multi-RHS and the learned preconditioner together.  The
-    network is trained on the workload-4 lattice (24^3x48, links drawn by the same recipe) at this
-    workload's mass, then its weights (which do not depend on the volume: the layers are gauge-covariant
-    stencils with site-independent channel weights) are loaded into a network on the large lattice.  The
-    solve is flexible CG with the network on all RHS, which hands each RHS to the mixed-precision CG when
-    its residual stalls."""
+def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, fp64_s):
+    """The third change on the large workload: mixed precision, multi-RHS and the learned preconditioner
+    together.  The network is trained on the 24^3x48 lattice (links drawn by the same recipe) at this
+    workload's mass, then its weights (the layers are gauge-covariant stencils with site-independent
+    channel weights, so they do not depend on the volume) are loaded into a network on the large
+    lattice.  The solve is flexible CG with the network on all RHS, which hands each RHS to the
+    mixed-precision CG when its residual stalls."""
     import torch
 
     from paper_1010_4782_amd.stagcg import Lattice, Net
@@ -221,10 +395,12 @@ def network_leg(a, p, mass, tol, rel_int, mp_s, fp64_s):
     t0 = time.perf_counter()
     tinfo = net_s.train(bs, xs, epochs=a.epochs, batch=8, lr=a.lr, loss=a.loss, mass=mass)
     t_train = time.perf_counter() - t0
-    print(f"# network trained on {dims4}: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} "
-          f"({npairs} pairs, {t_data:.1f} s data, {t_train:.1f} s training)", file=sys.stderr, flush=True)
+    log(f"network trained on {dims4}: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} "
+        f"({npairs} pairs, {t_data:.1f} s data, {t_train:.1f} s training)")
     weights = net_s.get_weights()
-    del bs, xs, net_s, small
+    del bs, xs, net_s
+    small.close()
+    p = s.probs[0]
     lat = p["lat"]
     lat.load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
     net = Net(lat, layers=w4["layers"], channels=w4["channels"], seed=1, hermitian=True)
@@ -236,18 +412,17 @@ def network_leg(a, p, mass, tol, rel_int, mp_s, fp64_s):
     _, info = lat.cg_solve(p["b"], mass, **kw)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t1
-    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    net.apply(p["b"][:1].contiguous())
+    net.apply(p["b"])
     torch.cuda.synchronize()
     t_apply = time.perf_counter() - t1
+    net.close()
     res = {"solve_s": t_solve, "iters": max(i["iters"] for i in info), "fell_back": sum(i["fell_back"] for i in info),
-           "true_resid": max(i["true_resid"] for i in info), "network_apply_ms_per_rhs": 1e3 * t_apply,
+           "true_resid": max(i["true_resid"] for i in info), "network_apply_ms_all_rhs": 1e3 * t_apply,
            "speedup_vs_mixed_only": mp_s / t_solve, "speedup_vs_fp64_cg": (fp64_s / t_solve) if fp64_s else None,
            "training": {"lattice": list(dims4), "pairs": npairs, "epochs": a.epochs, "data_s": t_data,
                         "train_s": t_train, "loss_first": tinfo["loss_first"], "loss_last": tinfo["loss_last"]}}
-    print(f"# network + mixed precision: {res['iters']} it, {t_solve:.3f} s, {res['fell_back']} RHS fell back",
-          file=sys.stderr, flush=True)
+    log(f"network + mixed precision: {res['iters']} it, {t_solve:.3f} s, {res['fell_back']} RHS fell back")
     return res
 
 
@@ -259,7 +434,7 @@ def run_shard_demo(a):
     import torch
 
     from paper_1010_4782_amd.stagcg import Lattice
-    from stag_inputs import WORKLOADS, workload_links, workload_sources
+    from stag_inputs import WORKLOADS, workload_links_device, workload_sources
 
     w = WORKLOADS[a.workload]
     dims, nrhs = w["lattices"][0]
@@ -269,11 +444,10 @@ def run_shard_demo(a):
         print(f"--shard-demo {P}: Lt = {Lt} must split into P slabs of an even number of slices", file=sys.stderr)
         return 2
     lt = Lt // P
-    fat, lng = workload_links(a.workload)
+    fat, lng = workload_links_device(a.workload)
     b = torch.from_numpy(workload_sources(a.workload)).cuda()
     lat = Lattice(dims)
-    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0, precs=("f64",),
-                   long_su3=not a.no_long_su3)
+    lat.load_links(fat, lng, -1.0 / 24.0, precs=("f64",), long_su3=not a.no_long_su3)
     del fat, lng
     S = lat.half // Lt
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -323,15 +497,16 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
+    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--prec", default="f16", choices=["f32", "f16"])
+    ap.add_argument("--fp64-steps", type=int, default=-1,
+                    help="timed plain FP64 CG solves after one warm-up (default: 2 on 48^3x144, 5 otherwise; 0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the workload's own solves: no 28^3x96 record, network leg or stream ceiling")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap the inner iterations (for counter-collection runs; the solve then stops early)")
-    ap.add_argument("--profile-every", type=int, default=10,
-                    help="bracket the Dslash launches of every k-th CG iteration with HIP events (each event "
-                         "record idles the GPU for a few us, so timing every iteration would slow the solve)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape instead of timing the candidates (for "
                          "counter-collection runs, where every dispatch is serialised and timings mean nothing)")
@@ -343,8 +518,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3, help="workloads 4 and 5: Adam step size")
     ap.add_argument("--loss", default="residual", choices=["residual", "solution"],
                     help="workloads 4 and 5: training loss")
-    ap.add_argument("--no-net", action="store_true",
-                    help="workload 5: skip the leg that adds the learned preconditioner")
+    ap.add_argument("--no-net", action="store_true", help="workload 5: skip the leg with the learned preconditioner")
     ap.add_argument("--shard-demo", type=int, default=0, metavar="P",
                     help="instead of the solve: split the workload's first lattice into P time slabs (one per GPU "
                          "of a multi-GPU run), exchange the 3-slice faces on this one GPU, apply the slab Dslash, "
@@ -356,176 +530,97 @@ def main(argv=None):
         return 2
 
     if a.workload == 4:
-        return run_learned_preconditioner(a, None)
+        return run_learned_preconditioner(a)
     if a.shard_demo:
         return run_shard_demo(a)
 
-    import numpy as np
     import torch
-
-    from paper_1010_4782_amd.stagcg import Lattice, cg_solve_batch
-    from stag_inputs import WORKLOADS, workload_links, workload_sources
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
-    w = WORKLOADS[a.workload]
-    tol = w["tol"]
-    rel_int = w.get("reliable_interval", 50)
-    t_gen = time.perf_counter()
-    dev = torch.device("cuda:0")
-    host, probs = [], []
-    for li, (dims, nrhs) in enumerate(w["lattices"]):
-        fat, lng = workload_links(a.workload, li)
-        b = workload_sources(a.workload, li)
-        lat = Lattice(dims)
-        probs.append(dict(lat=lat, dims=dims, nrhs=nrhs, fat=torch.from_numpy(fat).to(dev),
-                          lng=torch.from_numpy(lng).to(dev), b=torch.from_numpy(b).to(dev)))
-        host.append((fat, lng, b))
-        if a.workload != 2:
-            del fat, lng
-            host[-1] = None
-    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    masses = w["masses"]
-    precs = ("f64", a.prec)
-
-    def step(prec, profile=None):
-        """load_links on every lattice, then one batched solve per mass; returns the infos."""
-        profile = a.profile_every if profile is None else profile
-        for p in probs:
-            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=not a.no_long_su3)
-        torch.cuda.synchronize()  # load_links is asynchronous; keep its packing out of solve_s
-        infos = []
-        for m in masses:
-            batch = [(p["lat"], p["b"], [m] * p["nrhs"], None) for p in probs]
-            t_s = time.perf_counter()
-            xs, inf = cg_solve_batch(batch, tol=tol, prec=prec, reliable_interval=rel_int, profile=profile,
-                                     max_iter=a.max_iter, max_restarts=0 if a.max_iter else 5,
-                                     raise_on_fail=a.max_iter == 0, autotune=not a.no_autotune)
-            solve_time[0] += time.perf_counter() - t_s  # the call synchronises before returning
-            infos.append(inf)
-            if "source_sites" in w:  # propagators: the pion correlator of every source is part of the step
-                corr.append((probs[0]["lat"].pion_correlator(xs[0], m), xs[0]))
-        return infos
-
-    corr = []
-
-    solve_time = [0.0]
-
-    def dslash_rate(infos, prec):
-        """Algorithmic GB/s of the inner-iteration Dslash launches (plain and xpay averaged).  The bytes
-        are the compulsory ones of the whole batch: each lattice's links once per launch, whatever the
-        launch shape (a shape with fewer RHS per lane than the lattice has re-reads them: that is not
-        counted), plus every RHS's input and output vectors (and half a vector for the xpay read)."""
-        ms = sum(i[0]["dslash_ms"] for i in infos)
-        calls = sum(i[0]["dslash_calls"] for i in infos)
-        per_launch = 0.0
-        for p in probs:
-            site = link_bytes_per_site(prec, not a.no_long_su3) + p["nrhs"] * 2.5 * VEC[prec]
-            per_launch += p["lat"].half * site
-        avg = ms / max(calls, 1)
-        sites = sum(p["lat"].half * p["nrhs"] for p in probs)
-        return per_launch / (avg * 1e-3) / 1e9, avg, per_launch, calls, sites * FLOPS_PER_SITE / (avg * 1e-3) / 1e9
-
-    def paper_count_rate(prec, avg_ms):
-        """GB/s under the paper's own count (Sec. 2): every link, every one of the 16 neighbour colour
-        vectors and the output counted per site, no cache reuse; single RHS only."""
-        site = link_bytes_per_site(prec, not a.no_long_su3) + 17 * VEC[prec]
-        return sum(p["lat"].half for p in probs) * site / (avg_ms * 1e-3) / 1e9
-
-    for i in range(a.warmup):
-        step(a.prec)
-        print(f"# warmup {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    solve_time[0] = 0.0
-    t0 = time.perf_counter()
-    all_infos = []
-    for i in range(a.steps):
-        infos = step(a.prec)
-        all_infos.append(infos)
-        its = [max(x["iters"] for x in inf) for inf in infos]
-        res = max(x["true_resid"] for inf in infos for x in inf)
-        print(f"# step {i}: max iterations per batch {its}, worst true resid {res:.3e}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    mp_corr = corr[-1] if corr else None  # the last timed mixed-precision step's correlator
-    ms_per_step = 1e3 * elapsed / a.steps
-    flat = [inf for infos in all_infos for inf in infos]
-    achieved, avg_ms, bytes_per_launch, d_calls, gflops = dslash_rate(flat, a.prec)
-    last = all_infos[-1]
-    d0 = probs[0]["dims"]
-    shape = "+".join(f"{p['dims'][0]}^3x{p['dims'][3]}x{p['nrhs']}" if p["dims"][0] == p["dims"][2] else
-                     f"{'x'.join(map(str, p['dims']))}x{p['nrhs']}" for p in probs)
+    legs = {}
+    t_leg = time.perf_counter()
+    s = Solves(a.workload, a)
+    legs["inputs"] = time.perf_counter() - t_leg
+    log(f"inputs for {s.w['name']} in {legs['inputs']:.1f} s")
+    big = a.workload == 5
+    fp64_steps = 0 if a.no_fp64 else (a.fp64_steps if a.fp64_steps >= 0 else (2 if big else 5))
+    t_leg = time.perf_counter()
+    rec, infos = solve_record(s, a, a.steps, a.warmup, 0)
+    legs["mixed_precision"] = time.perf_counter() - t_leg
+    t_leg = time.perf_counter()
+    if fp64_steps:
+        i64, step64, solve64 = s.timed("f64", fp64_steps, 1, precs=("f64",))
+        r64 = s.dslash_rate(i64, "f64")
+        fp64 = {"step_s": step64, "solve_s": solve64, "timed_solves": fp64_steps, **s.summary(i64),
+                "dslash": {**r64, "frac_of_hbm_peak": r64["GBps"] / HBM_PEAK_GBPS}}
+        legs["fp64_cg"] = time.perf_counter() - t_leg
+        log(f"fp64 CG: {fp64['iters']} it, {step64:.3f} s per solve")
+    else:
+        fp64 = None
+    rate = rec["dslash_" + a.prec]
+    d0, n0 = s.probs[0]["dims"], s.probs[0]["nrhs"]
+    traffic = measured_traffic(a.prec, d0, not a.no_long_su3, n0) if len(s.probs) == 1 else None
     out = {
-        "metric": METRIC, "value": ms_per_step / 1e3, "unit": "s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
+        "metric": METRIC, "value": rec["step_s"], "unit": "s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * rec["step_s"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "storage": a.prec, "data": "synthetic",
-        "config": {"workload": f"{shape} (lattice x RHS), m={masses}, fat (0.6 SU(3) + noise) and Naik links, "
-                               f"true residual {tol}", "lattices": [list(p["dims"]) for p in probs],
-                   "nrhs": [p["nrhs"] for p in probs], "masses": masses, "tol": tol,
-                   "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every {rel_int} "
-                             f"iterations or after a 10x residual drop", "step": "load_links + solve",
+        "config": {"workload": f"{s.shape_name()} (lattice x RHS), m={s.w['masses']}, fat (0.6 SU(3) + noise) and "
+                               f"Naik links, true residual {s.tol}",
+                   "lattices": [list(p["dims"]) for p in s.probs], "nrhs": [p["nrhs"] for p in s.probs],
+                   "masses": s.w["masses"], "tol": s.tol,
+                   "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every {s.rel_int} "
+                             f"iterations or after a 10x residual drop, all RHS of a lattice in each launch",
+                   "step": "load_links + solve",
                    "long_links": "18 reals" if a.no_long_su3 else "12 reals (two rows, third rebuilt)"},
-        "solve_s": solve_time[0] / a.steps,
-        "mp_iters": [max(x["iters"] for x in inf) for inf in last],
-        "mp_reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
-        "mp_true_resid": max(x["true_resid"] for inf in last for x in inf),
-        "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"],
-                         "lds_stage": last[0][0]["dslash_lds"], "tile_order": last[0][0]["dslash_order"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(a.prec, d0, not a.no_long_su3) if len(probs) == 1 and probs[0]["nrhs"] == 1 else None,
-                     "kernel": f"k_dslash<{a.prec}> (plain and xpay launches)",
-                     "avg_launch_us": avg_ms * 1e3, "launches": d_calls, "bytes_per_launch": bytes_per_launch},
+        "solve_s": rec["solve_s"],
+        "mp_iters": rec["mp_iters"], "mp_reliable_updates": rec["mp_reliable_updates"],
+        "mp_true_resid": rec["mp_true_resid"], "dslash_shape": rec["mp_dslash_shape"],
+        "roofline": {"bound": "hbm", "achieved": rate["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": rate["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": f"k_dslash<{a.prec}>, {n0} RHS per launch (plain and xpay launches)",
+                     "avg_launch_us": rate["avg_launch_us"], "launches": rate["launches"],
+                     "bytes_per_launch": rate["bytes_per_launch"]},
+        "dslash_" + a.prec: rate,
     }
-    if not a.no_fp64:
-        torch.cuda.synchronize()
-        solve_time[0] = 0.0
-        t1 = time.perf_counter()
-        i64 = step("f64")
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
-        gbs64, avg64, _, _, gf64 = dslash_rate(i64, "f64")
-        out["fp64_cg_s"] = t64
-        out["fp64_solve_s"] = solve_time[0]
-        out["speedup_solve_only"] = solve_time[0] / out["solve_s"]
-        out["fp64_iters"] = [max(x["iters"] for x in inf) for inf in i64]
-        out["fp64_true_resid"] = max(x["true_resid"] for inf in i64 for x in inf)
-        out["speedup_vs_fp64_cg"] = t64 / (ms_per_step / 1e3)
-        out["dslash_f64"] = {"GBps": gbs64, "frac_of_hbm_peak": gbs64 / HBM_PEAK_GBPS, "avg_launch_us": avg64 * 1e3,
-                             "gflops": gf64, "shape": {"wg": i64[0][0]["dslash_wg"], "rhs_per_lane": i64[0][0]["dslash_rhs"],
-                                                       "lds_stage": i64[0][0]["dslash_lds"],
-                                                       "tile_order": i64[0][0]["dslash_order"]}}
-        print(f"# fp64 CG: {out['fp64_iters']} it, {t64:.3f} s, Dslash {gbs64:.0f} GB/s", file=sys.stderr, flush=True)
-    out["dslash_" + a.prec] = {"GBps": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBPS,
-                               "avg_launch_us": avg_ms * 1e3, "gflops": gflops}
-    if all(p["nrhs"] == 1 for p in probs):
-        out["dslash_" + a.prec]["GBps_paper_count"] = paper_count_rate(a.prec, avg_ms)
-    if a.workload == 5 and not a.no_net:
-        out["with_network"] = network_leg(a, probs[0], masses[0], tol, rel_int, out["solve_s"],
-                                          out.get("fp64_solve_s"))
-    if mp_corr is not None:
-        C, x0 = mp_corr
-        torch.cuda.synchronize()
-        Ch = C.cpu().numpy()
-        d0 = probs[0]["dims"]
-        diag = []
-        for s_, (sx, sy, sz, st) in enumerate(w["source_sites"]):
-            cb = (sx + d0[0] * (sy + d0[1] * (sz + d0[2] * st))) // 2
-            diag.append(sum(float(x0[3 * s_ + c, cb, c].real) for c in range(3)))
-        out["propagators"] = {
-            "sources": w["source_sites"], "correlator_t0_to_8": [list(map(float, row[:8])) for row in Ch],
-            "sum_rule_rel_err": max(abs(Ch[s_].sum() - diag[s_]) / diag[s_] for s_ in range(len(diag))),
-            "note": "C(t) = sum over time slice t of |G|^2, G_e = 2m chi, G_o = -D_oe chi; the sum over t equals "
-                    "sum_c chi^(c)(x0)_c"}
-    out["copy_ceiling"] = copy_ceiling(torch)
-    if not a.no_cpu_baseline and a.workload == 2:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        iters = out.get("fp64_iters", out["mp_iters"])[0]
-        fat, lng, b = host[0]
-        cb = cpu_baseline(fat, lng, b[0], probs[0]["dims"], masses[0], iters)
+    if fp64:
+        out["fp64_cg"] = fp64
+        out["fp64_cg_s"] = fp64["step_s"]
+        out["speedup_vs_fp64_cg"] = fp64["step_s"] / rec["step_s"]
+        out["speedup_solve_only"] = fp64["solve_s"] / rec["solve_s"]
+    host = b_host = None
+    if (big or a.workload == 2) and not a.no_cpu_baseline:
+        # host copies for the oracle, taken before the network leg reloads the links
+        host = s.host_links()
+        b_host = s.probs[0]["b"][0].cpu().numpy()
+    if big and not a.no_extras:
+        if not a.no_net:
+            t_leg = time.perf_counter()
+            out["with_network"] = network_leg(a, s, s.w["masses"][0], s.tol, s.rel_int, rec["solve_s"],
+                                              fp64["solve_s"] if fp64 else None)
+            legs["with_network"] = time.perf_counter() - t_leg
+        s.close()
+        t_leg = time.perf_counter()
+        s2 = Solves(2, a)
+        pl, _ = solve_record(s2, a, a.steps, a.warmup, 5, extra_precs=("f32",) if a.prec == "f16" else ())
+        pl["workload"] = f"{s2.shape_name()}, m={s2.w['masses']}"
+        out["paper_lattice"] = pl
+        s2.close()
+        legs["paper_lattice"] = time.perf_counter() - t_leg
+        t_leg = time.perf_counter()
+        out["stream_ceiling"] = stream_ceiling(torch)
+        legs["stream_ceiling"] = time.perf_counter() - t_leg
+    if host is not None:
+        log("cpu baseline (oracle) ...")
+        t_leg = time.perf_counter()
+        iters = (fp64["iters"] if fp64 else rec["mp_iters"])[0]
+        cb = cpu_baseline(host[0], host[1], b_host, s.w["lattices"][0][0], s.w["masses"][0], iters,
+                          nrhs=s.w["lattices"][0][1], workers=cpu_workers())
         cb["host"] = host_info()
         out["cpu_baseline"] = cb
+        legs["cpu_baseline"] = time.perf_counter() - t_leg
+    out["leg_seconds"] = legs
     print(json.dumps(out), flush=True)
     return 0
 

@@ -310,6 +310,13 @@ void stag_train_params_default(stag_train_params* prm);
 stag_status stag_net_train(stag_net_t net, const void* b, const void* x, int32_t npairs,
                            const stag_train_params* prm, stag_train_info* info, void* stream);
 
+/* Measurement helper (not part of the solver): stream `bytes` of device memory at buf with 16-byte
+ * non-temporal loads, one 32 KiB chunk per single-wave workgroup, all loads of a lane in flight at once,
+ * and write one XOR-folded word per chunk to sink (device uint32 [bytes / 32768]).  It is the read-only
+ * HBM ceiling the bandwidth-bound kernels are compared with.  bytes must be a positive multiple of
+ * 32768; NULL pointers or another size: STAG_ERR_ARG.  Asynchronous on `stream`. */
+stag_status stag_stream_read(const void* buf, int64_t bytes, uint32_t* sink, void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* stag_last_error(void);
 

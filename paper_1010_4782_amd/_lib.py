@@ -134,6 +134,7 @@ SIGNATURES = {
     "stag_slice_norm2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                    C.c_void_p, C.c_void_p]),
     "stag_pion_correlator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p]),
+    "stag_stream_read": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "stag_tune_cache_save": (C.c_int, [C.c_char_p]),
     "stag_tune_cache_load": (C.c_int, [C.c_char_p]),
     "stag_net_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64,

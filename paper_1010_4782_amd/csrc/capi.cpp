@@ -559,6 +559,15 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   STAG_GUARD_END
 }
 
+stag_status stag_stream_read(const void* buf, int64_t bytes, uint32_t* sink, void* stream) {
+  STAG_GUARD_BEGIN
+  if (!buf || !sink) return arg_error("buf and sink must not be NULL");
+  if (bytes <= 0 || bytes % stream_read_chunk_bytes()) return arg_error("bytes must be a positive multiple of 32768");
+  STAG_HIP_TRY(launch_stream_read(buf, (long)bytes, sink, reinterpret_cast<hipStream_t>(stream)));
+  return STAG_OK;
+  STAG_GUARD_END
+}
+
 stag_status stag_tune_cache_save(const char* path) {
   STAG_GUARD_BEGIN
   if (!path) return arg_error("path is NULL");

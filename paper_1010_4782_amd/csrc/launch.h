@@ -101,4 +101,9 @@ hipError_t launch_convert_to_f64(int prec, const void* in, void* out, long nsite
 
 Geo make_geo(const int dims[4]);
 
+// Read-only streaming probe (probe.hip): bytes must be a positive multiple of stream_read_chunk_bytes();
+// sink receives one word per chunk.
+long stream_read_chunk_bytes();
+hipError_t launch_stream_read(const void* buf, long bytes, unsigned* sink, hipStream_t st);
+
 }  // namespace stag

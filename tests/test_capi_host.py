@@ -100,6 +100,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.stag_apply_m(None, None, None, None, 1, None) == 1
     assert lib.stag_slice_norm2(None, None, 3, 3, 1.0, 0, None, None) == 1
     assert lib.stag_pion_correlator(None, None, 1, 0.1, None, None) == 1
+    assert lib.stag_stream_read(None, 32768, None, None) == 1
     assert lib.stag_lattice_info(None, None, None) == 1
 
 
