@@ -73,7 +73,7 @@ class StagInfo(C.Structure):
 
 class StagShape(C.Structure):
     _fields_ = [("wg", C.c_int32), ("rhs_per_lane", C.c_int32), ("lds_stage", C.c_int32), ("tile_order", C.c_int32),
-                ("us", C.c_double)]
+                ("t_chunks", C.c_int32), ("us", C.c_double)]
 
 
 class StagProblem(C.Structure):

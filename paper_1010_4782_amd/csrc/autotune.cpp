@@ -1,6 +1,7 @@
 // Autotuner for the Dslash launch shape: workgroup size (sites per workgroup),
 // right-hand sides per lane, LDS staging of the x/y neighbour window and the
-// tile order (lattice order or XCD blocks).  Candidates are timed with HIP events on the caller's
+// tile order (lattice order or XCD blocks), and, for FP16 batches of 8k right-hand sides, the
+// time-streaming kernel with its number of time chunks.  Candidates are timed with HIP events on the caller's
 // stream on the real buffers of the call; winners are kept per key
 // (lattice shapes, right-hand sides, storage precision) in memory and can be saved
 // to / loaded from a small JSON file.
@@ -95,28 +96,30 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
   DslashShape best{};
   float best_us = 1e30f;
   const int reps = 5;
-  for (int wg : {64, 128, 256}) {
-    for (int r = 1; r <= rmax && e == hipSuccess; r *= 2) {
-      for (int v = 0; v < 4; ++v) {
-        const DslashShape sh{wg, r, v & 1, v >> 1};
-        if (!dslash_shape_valid(bh, prec, sh)) continue;
-        for (int w = 0; w < 2 && e == hipSuccess; ++w)
-          e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int i = 0; i < reps && e == hipSuccess; ++i)
-          e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) break;
-        const float us = 1e3f * ms / reps;
-        if (all) all->push_back({sh, us});
-        if (us < best_us) {
-          best_us = us;
-          best = sh;
-        }
-      }
+  std::vector<DslashShape> cands;
+  for (int wg : {64, 128, 256})
+    for (int r = 1; r <= rmax; r *= 2)
+      for (int v = 0; v < 4; ++v) cands.push_back(DslashShape{wg, r, v & 1, v >> 1});
+  for (int r : {8, 4})
+    for (int chunks : {1, 2, 4}) cands.push_back(DslashShape{64, r, 0, 2, chunks});
+  for (const DslashShape& sh : cands) {
+    if (e != hipSuccess) break;
+    if (!dslash_shape_valid(bh, prec, sh)) continue;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w)
+      e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+      e = launch_dslash(bh, prec, EPI_PLAIN, 1, in_id, out_id, 0, 0, 3, sh, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    const float us = 1e3f * ms / reps;
+    if (all) all->push_back({sh, us});
+    if (us < best_us) {
+      best_us = us;
+      best = sh;
     }
   }
   (void)hipEventDestroy(e0);
@@ -136,15 +139,15 @@ bool save_table(const char* path) {
   size_t i = 0;
   for (const auto& kv : g_table) {
     f << "  \"" << kv.first << "\": [" << kv.second.wg << ", " << kv.second.r << ", " << kv.second.lds << ", "
-      << kv.second.order << "]"
+      << kv.second.order << ", " << kv.second.chunks << "]"
       << (++i < g_table.size() ? ",\n" : "\n");
   }
   f << "}\n";
   return (bool)f;
 }
 
-// Reads the format save_table writes: one "key": [wg, r, lds, order] entry per line (lds and order may
-// be absent: 0).
+// Reads the format save_table writes: one "key": [wg, r, lds, order, chunks] entry per line (lds and
+// order may be absent: 0; chunks: 1).
 bool load_table(const char* path, int* n_loaded) {
   std::ifstream f(path);
   if (!f) return false;
@@ -157,13 +160,13 @@ bool load_table(const char* path, int* n_loaded) {
     const size_t q1 = line.find('"', q0 + 1);
     const size_t b0 = line.find('[', q1);
     if (q1 == std::string::npos || b0 == std::string::npos) return false;
-    int wg = 0, r = 0, lds = 0, order = 0;
-    const int got = std::sscanf(line.c_str() + b0, "[%d , %d , %d , %d]", &wg, &r, &lds, &order);
+    int wg = 0, r = 0, lds = 0, order = 0, chunks = 1;
+    const int got = std::sscanf(line.c_str() + b0, "[%d , %d , %d , %d , %d]", &wg, &r, &lds, &order, &chunks);
     if (got < 2) return false;
     if ((wg != 64 && wg != 128 && wg != 256) || (r != 1 && r != 2 && r != 4 && r != 8) || (lds != 0 && lds != 1) ||
-        (order != 0 && order != 1))
+        (order < 0 || order > 2) || chunks < 1 || chunks > 64)
       return false;
-    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r, lds, order};
+    tmp[line.substr(q0 + 1, q1 - q0 - 1)] = DslashShape{wg, r, lds, order, chunks};
     ++n;
   }
   std::lock_guard<std::mutex> lk(g_mu);

@@ -154,7 +154,7 @@ stag_status ring_release(Ctl& c, const RingEntry& e, hipStream_t st) {
 // Set up a single-problem batch whose table, scalars and partials live in a ring entry.
 stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* const* vec_override, hipStream_t st,
                          BatchHost& bh, RingEntry& e, const Geo* geo_override = nullptr) {
-  const int pstride = ceil_div(L->g.half, kWave);
+  const int pstride = ceil_div(L->g.half, kWave / 2);  // 32-site partials of the time-streaming kernel
   const size_t off_scal = (sizeof(ProbDev) + 255) & ~size_t(255);
   const size_t off_part = off_scal + ((sizeof(Scal) * nrhs + 255) & ~size_t(255));
   const size_t need = off_part + sizeof(double) * (size_t)nrhs * kPartialSlots * pstride;
@@ -173,7 +173,7 @@ stag_status single_batch(stag_lattice_s* L, int nrhs, const double* mass, void* 
     sc[r] = z;
   }
   STAG_HIP_TRY(hipMemcpyAsync(e.dev, e.host, off_part, hipMemcpyHostToDevice, st));
-  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh, pd.g.L[1], pd.g.L[2]});
+  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh, pd.g.L[1], pd.g.L[2], pd.g.L[3], pd.g.t_open});
   bh.d_probs = reinterpret_cast<const ProbDev*>(e.dev);
   bh.d_scal = reinterpret_cast<Scal*>(e.dev + off_scal);
   bh.d_partial = reinterpret_cast<double*>(e.dev + off_part);
@@ -516,13 +516,15 @@ stag_status stag_tune_dslash(stag_lattice_t lat, int32_t prec, int32_t nrhs, sta
   if (s != STAG_OK) return s;
   float best_us = 0.f;
   for (const auto& t : timed)
-    if (t.first.wg == b.wg && t.first.r == b.r && t.first.lds == b.lds && t.first.order == b.order) best_us = t.second;
-  if (best) *best = stag_shape{b.wg, b.r, b.lds, b.order, best_us};
+    if (t.first.wg == b.wg && t.first.r == b.r && t.first.lds == b.lds && t.first.order == b.order &&
+        t.first.chunks == b.chunks)
+      best_us = t.second;
+  if (best) *best = stag_shape{b.wg, b.r, b.lds, b.order, b.chunks, best_us};
   if (all) {
     int n = 0;
     for (const auto& t : timed) {
       if (n >= max_all) break;
-      all[n++] = stag_shape{t.first.wg, t.first.r, t.first.lds, t.first.order, t.second};
+      all[n++] = stag_shape{t.first.wg, t.first.r, t.first.lds, t.first.order, t.first.chunks, t.second};
     }
     if (n_all) *n_all = n;
   }
@@ -536,11 +538,11 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   if (nrhs < 1) return arg_error("nrhs must be >= 1");
   if (prec < STAG_F64 || prec > STAG_F16) return arg_error("prec must be STAG_F64, STAG_F32 or STAG_F16");
   BatchHost bh;
-  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0, lat->g.Xh, lat->g.L[1], lat->g.L[2]});
+  bh.probs.assign(1, HostProb{lat->g.half, nrhs, 0, lat->g.Xh, lat->g.L[1], lat->g.L[2], lat->g.L[3], 0});
   bh.long12 = lat->g.long12 != 0;
   const std::string key = single_key(bh, lat, prec);
   if (!shape || shape->wg == 0) {
-    pin_shape(key, DslashShape{0, 1, 0, 0});
+    pin_shape(key, DslashShape{0, 1, 0, 0, 1});
     return STAG_OK;
   }
   const int wg = shape->wg, r = shape->rhs_per_lane;
@@ -548,12 +550,17 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   if (r != 1 && r != 2 && r != 4 && r != 8) return arg_error("rhs_per_lane must be 1, 2, 4 or 8");
   if (nrhs % r) return arg_error("rhs_per_lane must divide nrhs");
   if (shape->lds_stage != 0 && shape->lds_stage != 1) return arg_error("lds_stage must be 0 or 1");
-  if (shape->tile_order != 0 && shape->tile_order != 1) return arg_error("tile_order must be 0 or 1");
-  const DslashShape sh{wg, r, shape->lds_stage, shape->tile_order};
+  if (shape->tile_order < 0 || shape->tile_order > 2) return arg_error("tile_order must be 0, 1 or 2");
+  const int chunks = shape->tile_order == 2 ? shape->t_chunks : 1;
+  if (chunks < 1) return arg_error("t_chunks must be >= 1 with tile_order 2");
+  const DslashShape sh{wg, r, shape->lds_stage, shape->tile_order, chunks};
   if (!dslash_shape_valid(bh, prec, sh))
-    return arg_error(sh.order ? "tile_order 1 needs Lz divisible by 8 and wg dividing Ly x Lx / 2 (and, staged, "
-                                "an LDS window within 64 KiB)"
-                              : "the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
+    return arg_error(sh.order == 2 ? "tile_order 2 needs FP16, wg 64, rhs_per_lane 8 or 4, no LDS staging, nrhs "
+                                     "divisible by 8, Lx Ly Lz / 2 divisible by the sites per wave (64 or 32) and Lt "
+                                     "by 2 t_chunks"
+                     : sh.order ? "tile_order 1 needs Lz divisible by 8 and wg dividing Ly x Lx / 2 (and, staged, "
+                                  "an LDS window within 64 KiB)"
+                                : "the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
   pin_shape(key, sh);
   return STAG_OK;
   STAG_GUARD_END

@@ -340,6 +340,20 @@ template <> __device__ __forceinline__ void raw_spinor_load<P32>(const void* bas
 template <> __device__ __forceinline__ void raw_spinor_load<P16>(const void* base, long s, RawSpinor<P16>& r) {
   r.w = as_global<u4v>(base)[s];
 }
+// The same raw reads from a colour-vector array staged in LDS (index s relative to the staged window).
+template <int P> __device__ __forceinline__ void raw_spinor_lds(const char* base, int s, RawSpinor<P>& r) {
+  if constexpr (P == P64) {
+    const d2v* p = reinterpret_cast<const d2v*>(base) + 3 * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.c[c] = p[c];
+  } else if constexpr (P == P32) {
+    const f2v* p = reinterpret_cast<const f2v*>(base) + 3 * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.c[c] = p[c];
+  } else {
+    r.w = reinterpret_cast<const u4v*>(base)[s];
+  }
+}
 // lsc: the FP16 link scale folded into the vector (see load_spinor_ls); ignored for FP32 / FP64.
 template <int P>
 __device__ __forceinline__ void raw_spinor_decode(const RawSpinor<P>& r, float lsc, Cx<typename RealOf<P>::T> v[3]) {
@@ -368,6 +382,87 @@ __device__ __forceinline__ void rebuild_row3(Cx<T> u[9], T inv_s) {
     const T im = a[i1].re * b[i2].im + a[i1].im * b[i2].re - (a[i2].re * b[i1].im + a[i2].im * b[i1].re);
     u[6 + i] = Cx<T>{re * inv_s, -im * inv_s};
   }
+}
+
+// ---- FP16 products on the binary16 codes (v_dot2_f32_f16) ----------------------------------------
+// A binary16 link element u = (ur, ui) and colour component v = (vr, vi), each a pair of codes in one
+// 32-bit word (real part in the low half):
+//   Re(u v) = ur vr - ui vi = dot((ur, -ui), v),   Im(u v) = ui vr + ur vi = dot((ui, ur), v),
+// two dot2 instructions per complex product, each multiplying two codes exactly and adding in binary32.
+// The conjugated-sign word (ur, -ui) and the swapped word (ui, ur) are formed once per link element and
+// serve every right-hand side.  The product of a link and a vector is taken in code units and then
+// scaled by (link scale x vector scale).
+__device__ __forceinline__ float fdot2(unsigned a, unsigned b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2v, a), __builtin_bit_cast(h2v, b), c, false);
+}
+__device__ __forceinline__ unsigned neg_hi(unsigned w) { return w ^ 0x80000000u; }                       // (a, b) -> (a, -b)
+__device__ __forceinline__ unsigned swap_halves(unsigned w) { return __builtin_amdgcn_alignbit(w, w, 16); }  // (a, b) -> (b, a)
+
+// A link in the dot2 form: its stored code words with the sign of the imaginary part flipped and with
+// their halves swapped (9 each, or 6 for a two-row three-hop link), and, for a two-row link, its rebuilt
+// third row in binary32 code units.
+struct LinkH {
+  unsigned p[9], s[9];
+  Cx<float> w[3];
+};
+
+template <int ROWS>
+__device__ __forceinline__ void link_h_prepare(const RawLink<P16>& r, float row3_factor, LinkH& L) {
+  const unsigned e[9] = {r.q0.x, r.q0.y, r.q0.z, r.q0.w, r.q1.x, r.q1.y, r.q1.z, r.q1.w, r.t};
+#pragma unroll
+  for (int i = 0; i < 3 * ROWS; ++i) {
+    L.p[i] = neg_hi(e[i]);
+    L.s[i] = swap_halves(e[i]);
+  }
+  if constexpr (ROWS == 2) {
+    // third row of s U (U in SU(3)) from the first two, in code units (the factor carries 1/s and the
+    // link scale, as in rebuild_row3)
+    Cx<float> u[9];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) u[i] = unpack_h2(e[i], 1.f);
+    rebuild_row3(u, row3_factor);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L.w[i] = u[6 + i];
+  }
+}
+
+// acc += s (U v) for a link in dot2 form and the codes v0, v1, v2 of a colour vector; s = link scale x
+// vector scale.  Per row: three chained dot2 for the real and three for the imaginary part (binary32
+// code units), then one FMA each into the accumulator.
+template <int ROWS>
+__device__ __forceinline__ void matvec_h_acc(const LinkH& L, unsigned v0, unsigned v1, unsigned v2, float s,
+                                             Cx<float> acc[3]) {
+#pragma unroll
+  for (int a = 0; a < ROWS; ++a) {
+    float re = fdot2(L.p[3 * a], v0, 0.f);
+    re = fdot2(L.p[3 * a + 1], v1, re);
+    re = fdot2(L.p[3 * a + 2], v2, re);
+    float im = fdot2(L.s[3 * a], v0, 0.f);
+    im = fdot2(L.s[3 * a + 1], v1, im);
+    im = fdot2(L.s[3 * a + 2], v2, im);
+    acc[a].re = fmaf(s, re, acc[a].re);
+    acc[a].im = fmaf(s, im, acc[a].im);
+  }
+  if constexpr (ROWS == 2) {
+    const Cx<float> c[3] = {unpack_h2(v0, 1.f), unpack_h2(v1, 1.f), unpack_h2(v2, 1.f)};
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      re = fmaf(L.w[b].re, c[b].re, re);
+      re = fmaf(-L.w[b].im, c[b].im, re);
+      im = fmaf(L.w[b].re, c[b].im, im);
+      im = fmaf(L.w[b].im, c[b].re, im);
+    }
+    acc[2].re = fmaf(s, re, acc[2].re);
+    acc[2].im = fmaf(s, im, acc[2].im);
+  }
+}
+
+// Order in which the FP16 Dslash accumulates the 16 matrices of an output site: the time hops
+// -3, -1 first, then the x, y, z matrices, then the time hops +1, +3.  It is the order in which the
+// time-streaming kernel (dslash_t.hip) receives them, so every FP16 launch shape gives the same bits.
+__host__ __device__ constexpr int f16_link_order(int i) {
+  return i == 0 ? 15 : (i == 1 ? 13 : (i < 14 ? i - 2 : (i == 14 ? 12 : 14)));
 }
 
 // Load the packed matrix k of the output site in block blk (lane = site % 64); C12: the three-hop

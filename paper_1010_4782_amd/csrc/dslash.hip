@@ -17,22 +17,8 @@
 
 namespace stag {
 
-// Issue the loads of link k of this lane's site and of the colour vector it multiplies.
-template <int P, bool C12>
-__device__ __forceinline__ void dslash_issue(int k, const Site& s, const Geo& g, const char* lbase, long blk, int lane,
-                                             const char* in, RawLink<P>& l, RawSpinor<P>& v) {
-  const int mu = k >> 2, j = k & 3;
-  const int nb = neighbour(s, g, mu, j < 2 ? g.h1[mu] : g.h3[mu], (j & 1) == 0);
-  const char* slot = lbase + link_slot_offset(P, C12, blk, k);
-  if (C12 && j >= 2)
-    raw_link_load<P, 2>(slot, lane, l);
-  else
-    raw_link_load<P, 3>(slot, lane, l);
-  raw_spinor_load<P>(in, nb, v);
-}
-
-// The same for R right-hand sides per lane: one link, the R colour vectors at its neighbour (only for
-// the active RHS; `on` is uniform over the workgroup).
+// Issue the loads of link k of this lane's site and of the R colour vectors it multiplies (only for the
+// active RHS; `on` is uniform over the workgroup).
 template <int P, bool C12, int R>
 __device__ __forceinline__ void dslash_issue_r(int k, const Site& s, const Geo& g, const char* lbase, long blk,
                                                int lane, const char* in, long rstride_in, const bool on[R],
@@ -47,6 +33,28 @@ __device__ __forceinline__ void dslash_issue_r(int k, const Site& s, const Geo& 
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (on[r]) raw_spinor_load<P>(in + r * rstride_in, nb, v[r]);
+}
+
+// The i-th matrix an output site accumulates: f16_link_order for FP16, index order otherwise.
+template <int P> __device__ __forceinline__ constexpr int link_at(int i) { return P == P16 ? f16_link_order(i) : i; }
+
+// FP16: acc += (link scale x vector scale) (L v) for one colour vector v of a link L in dot2 form.
+template <bool C12>
+__device__ __forceinline__ void apply_link_h(const LinkH& L, bool long_link, const RawSpinor<P16>& v, float lsc,
+                                             Cx<float> acc[3]) {
+  const float s = lsc * __uint_as_float(v.w.w);
+  if (C12 && long_link)
+    matvec_h_acc<2>(L, v.w.x, v.w.y, v.w.z, s, acc);
+  else
+    matvec_h_acc<3>(L, v.w.x, v.w.y, v.w.z, s, acc);
+}
+template <bool C12>
+__device__ __forceinline__ void prepare_link_h(const RawLink<P16>& lr, bool long_link, float lsc, float row3,
+                                               LinkH& L) {
+  if (C12 && long_link)
+    link_h_prepare<2>(lr, row3 * lsc, L);
+  else
+    link_h_prepare<3>(lr, 0.f, L);
 }
 
 // Prefetch distance (links) of the single right-hand-side kernel, per storage precision, from a
@@ -166,87 +174,99 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
     __syncthreads();
   }
 
+  // The FP16 launches take the 16 matrices in f16_link_order and multiply binary16 codes with dot2
+  // (apply_link_h); FP32 and FP64 take them in index order with decoded matrices.  Either way every
+  // launch shape of a precision does the same arithmetic in the same order.
   if constexpr (PF > 0) {
-    // Software pipeline over the 16 links: the loads of link k + PF are issued while link k is
+    // Software pipeline over the 16 links: the loads of link i + PF are issued while link i is
     // multiplied.  An empty volatile asm that takes the accumulators closes each stage: the
-    // products of link k must be done before it and the loads issued after it cannot move above
+    // products of link i must be done before it and the loads issued after it cannot move above
     // it, so the compiler can neither hoist all loads to the top nor sink them to their uses.
-    if constexpr (R > 1) {
-      RawLink<P> lb[PF];
-      RawSpinor<P> vb[PF][R];
+    RawLink<P> lb[PF];
+    RawSpinor<P> vb[PF][R];
 #pragma unroll
-      for (int k = 0; k < PF; ++k)
-        dslash_issue_r<P, C12, R>(k, s, g, lbase, blk, lane, in, rstride_in, on, lb[k], vb[k]);
+    for (int i = 0; i < PF; ++i)
+      dslash_issue_r<P, C12, R>(link_at<P>(i), s, g, lbase, blk, lane, in, rstride_in, on, lb[i], vb[i]);
 #pragma unroll
-      for (int k = 0; k < kLinks; ++k) {
-        const int mu = k >> 2, j = k & 3;
+    for (int i = 0; i < kLinks; ++i) {
+      const int k = link_at<P>(i);
+      const int mu = k >> 2, j = k & 3;
+      const float lsc = j < 2 ? sc_fat : sc_long;
+      if constexpr (P == P16) {
+        LinkH L;
+        prepare_link_h<C12>(lb[i % PF], j >= 2, lsc, (float)long_sign(s, g, mu, j == 2) * cn_inv, L);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (on[r]) apply_link_h<C12>(L, j >= 2, vb[i % PF][r], lsc, acc[r]);
+      } else {
         Cx<T> u[9];
-        const float lsc = j < 2 ? sc_fat : sc_long;
         if (C12 && j >= 2) {
-          raw_link_decode<P, 2>(lb[k % PF], 1.f, u);
-          rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv * (T)lsc);
+          raw_link_decode<P, 2>(lb[i % PF], 1.f, u);
+          rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv);
         } else {
-          raw_link_decode<P, 3>(lb[k % PF], 1.f, u);
+          raw_link_decode<P, 3>(lb[i % PF], 1.f, u);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (!on[r]) continue;
           Cx<T> v[3];
-          raw_spinor_decode<P>(vb[k % PF][r], lsc, v);
+          raw_spinor_decode<P>(vb[i % PF][r], 1.f, v);
           matvec_acc(u, v, acc[r]);
         }
-        if (k + PF < kLinks)
-          dslash_issue_r<P, C12, R>(k + PF, s, g, lbase, blk, lane, in, rstride_in, on, lb[k % PF], vb[k % PF]);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          asm volatile("" : "+v"(acc[r][0].re), "+v"(acc[r][0].im), "+v"(acc[r][1].re), "+v"(acc[r][1].im),
-                       "+v"(acc[r][2].re), "+v"(acc[r][2].im));
       }
-    } else {
-    RawLink<P> lb[PF];
-    RawSpinor<P> vb[PF];
+      if (i + PF < kLinks)
+        dslash_issue_r<P, C12, R>(link_at<P>(i + PF), s, g, lbase, blk, lane, in, rstride_in, on, lb[i % PF],
+                                  vb[i % PF]);
 #pragma unroll
-    for (int k = 0; k < PF; ++k) dslash_issue<P, C12>(k, s, g, lbase, blk, lane, in, lb[k], vb[k]);
+      for (int r = 0; r < R; ++r)
+        asm volatile("" : "+v"(acc[r][0].re), "+v"(acc[r][0].im), "+v"(acc[r][1].re), "+v"(acc[r][1].im),
+                     "+v"(acc[r][2].re), "+v"(acc[r][2].im));
+    }
+  } else {
 #pragma unroll
-    for (int k = 0; k < kLinks; ++k) {
+    for (int i = 0; i < kLinks; ++i) {
+      const int k = link_at<P>(i);
       const int mu = k >> 2, j = k & 3;
-      Cx<T> u[9], v[3];
-      const float lsc = j < 2 ? sc_fat : sc_long;
-      if (C12 && j >= 2) {
-        raw_link_decode<P, 2>(lb[k % PF], 1.f, u);
-        // the rebuilt row is in the same code units as the two stored ones: one more factor of the scale
-        rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv * (T)lsc);
-      } else {
-        raw_link_decode<P, 3>(lb[k % PF], 1.f, u);
-      }
-      raw_spinor_decode<P>(vb[k % PF], lsc, v);
-      matvec_acc(u, v, acc[0]);
-      if (k + PF < kLinks) dslash_issue<P, C12>(k + PF, s, g, lbase, blk, lane, in, lb[k % PF], vb[k % PF]);
-      asm volatile("" : "+v"(acc[0][0].re), "+v"(acc[0][0].im), "+v"(acc[0][1].re), "+v"(acc[0][1].im),
-                   "+v"(acc[0][2].re), "+v"(acc[0][2].im));
-    }
-    }
-  } else
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
       const int hop = j < 2 ? g.h1[mu] : g.h3[mu];
       const int nb = neighbour(s, g, mu, hop, (j & 1) == 0);
-      Cx<T> u[9];
       const float lsc = j < 2 ? sc_fat : sc_long;
-      load_link<P, C12>(lbase, blk, 4 * mu + j, lane, 1.f, u);
-      if (C12 && j >= 2) rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv * (T)lsc);
       const bool from_lds = LDS && mu < 2 && (unsigned)(nb - w0) < (unsigned)wn;
+      const char* slot = lbase + link_slot_offset(P, C12, blk, k);
+      RawLink<P> lr;
+      if (C12 && j >= 2)
+        raw_link_load<P, 2>(slot, lane, lr);
+      else
+        raw_link_load<P, 3>(slot, lane, lr);
+      RawSpinor<P> vr[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!on[r]) continue;
-        Cx<T> v[3];
         if (from_lds)
-          load_spinor_lds<P>(dslash_window + r * wn * SB, nb - w0, lsc, v);
+          raw_spinor_lds<P>(dslash_window + r * wn * SB, nb - w0, vr[r]);
         else
-          load_spinor_ls<P>(in + r * rstride_in, nb, lsc, v);
-        matvec_acc(u, v, acc[r]);
+          raw_spinor_load<P>(in + r * rstride_in, nb, vr[r]);
+      }
+      if constexpr (P == P16) {
+        LinkH L;
+        prepare_link_h<C12>(lr, j >= 2, lsc, (float)long_sign(s, g, mu, j == 2) * cn_inv, L);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (on[r]) apply_link_h<C12>(L, j >= 2, vr[r], lsc, acc[r]);
+      } else {
+        Cx<T> u[9];
+        if (C12 && j >= 2) {
+          raw_link_decode<P, 2>(lr, 1.f, u);
+          rebuild_row3(u, (T)long_sign(s, g, mu, j == 2) * cn_inv);
+        } else {
+          raw_link_decode<P, 3>(lr, 1.f, u);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!on[r]) continue;
+          Cx<T> v[3];
+          raw_spinor_decode<P>(vr[r], 1.f, v);
+          matvec_acc(u, v, acc[r]);
+        }
       }
     }
   }
@@ -380,6 +400,7 @@ size_t dslash_lds_bytes(const BatchHost& bh, int prec, const DslashShape& sh) {
 }
 
 bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh) {
+  if (sh.order == 2) return prec == P16 && sh.wg == 64 && sh.lds == 0 && dslash_t_ok(bh, sh.r, sh.chunks);
   if (sh.wg != 64 && sh.wg != 128 && sh.wg != 256) return false;
   if (sh.r != 1 && sh.r != 2 && sh.r != 4 && sh.r != 8) return false;
   if (sh.order != 0 && sh.order != 1) return false;
@@ -392,6 +413,7 @@ bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh) {
 hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
                          int b_id, int gate, const DslashShape& sh, hipStream_t st) {
   if (!dslash_shape_valid(bh, prec, sh)) return hipErrorInvalidValue;
+  if (sh.order == 2) return launch_dslash_t(bh, epi, out_par, in_id, out_id, x_id, gate, sh.r, sh.chunks, st);
   const Batch B = make_batch(bh, sh.wg, sh.r);
   const int nblk = B.block_start[B.nprob];
   if (nblk == 0) return hipSuccess;

@@ -21,7 +21,11 @@ struct HostProb {
   int slot0;
   int xh = 0;  // Lx / 2 (width of the LDS window margin of a staged Dslash)
   int ny = 0, nz = 0;  // Ly, Lz (whether the XCD-block tile order fits the lattice)
+  int lt = 0;          // Lt (of the slab, for a slab launch)
+  int t_open = 0;      // 1: a time slab with ghost slices (stag_dslash_slab)
 };
+
+constexpr int kTGroupRhs = 8;  // right-hand sides per site of a time-streaming wave
 
 constexpr size_t kMaxDslashLds = 64 * 1024;  // LDS a staged Dslash workgroup may use
 
@@ -44,14 +48,24 @@ struct DslashShape {
   int wg = 256;
   int r = 1;
   int lds = 0;  // 1: stage the x and y neighbour colour vectors of a workgroup's sites in LDS
-  int order = 0;  // 1: XCD-block tile order (each XCD sweeps t through one z block)
+  int order = 0;  // 1: XCD-block tile order (each XCD sweeps t through one z block);
+                  // 2: the time-streaming FP16 kernel (dslash_t.hip): wg 64 (one wave), r 8 (one lane per
+                  //    site) or r 4 (two lanes per site, 32 sites per wave)
+  int chunks = 1; // order 2: the time extent is walked in this many chunks (one wave per chunk)
 };
+
+// Sites per reduction partial of the xpay launch of this shape (the finalize's producer_wg).
+inline int partial_wg(const DslashShape& s) { return s.order == 2 ? s.wg / (kTGroupRhs / s.r) : s.wg; }
 
 // Bytes of LDS a staged launch of this shape needs (0 if unstaged), and whether it fits.
 size_t dslash_lds_bytes(const BatchHost& bh, int prec, const DslashShape& sh);
 bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh);
 hipError_t launch_dslash(const BatchHost& bh, int prec, int epi, int out_par, int in_id, int out_id, int x_id,
                          int b_id, int gate, const DslashShape& sh, hipStream_t st);
+// The time-streaming FP16 kernel (plain or xpay + <d, Ad> epilogue) and whether a batch fits it.
+bool dslash_t_ok(const BatchHost& bh, int r, int chunks);
+hipError_t launch_dslash_t(const BatchHost& bh, int epi, int out_par, int in_id, int out_id, int x_id, int gate,
+                           int r, int chunks, hipStream_t st);
 
 // Vector stages of the solvers (every one is one launch over all slots of the batch).
 hipError_t launch_norm2(const BatchHost& bh, int prec, int v_id, int kind, int gate, int wg, hipStream_t st);

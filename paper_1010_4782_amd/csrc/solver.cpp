@@ -100,7 +100,7 @@ hipError_t iteration(Run& R, int x_prec, int x_id, double* d_hist) {
   if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape, R.st);
   if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape, R.st);
   if (e == hipSuccess) e = record(R, samp);
-  if (e == hipSuccess) e = launch_finalize(R.bh, FIN_ALPHA, 0, 2, R.shape.wg, d_hist, R.hist_len, R.st);
+  if (e == hipSuccess) e = launch_finalize(R.bh, FIN_ALPHA, 0, 2, partial_wg(R.shape), d_hist, R.hist_len, R.st);
   if (e == hipSuccess) e = launch_update_r(R.bh, P, kVecWG, R.st);
   if (e == hipSuccess) e = launch_finalize(R.bh, FIN_BETA, 1, 1, kVecWG, d_hist, R.hist_len, R.st);
   if (e == hipSuccess) e = launch_update_xd(R.bh, P, x_prec, x_id, kVecWG, R.st);
@@ -306,14 +306,14 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     pd.vec[V_B] = const_cast<void*>(probs[p].b);
     pd.vec[V_X] = probs[p].x;
     table[p] = pd;
-    R.bh.probs.push_back(HostProb{L->g.half, n, slot, L->g.Xh, L->g.L[1], L->g.L[2]});
+    R.bh.probs.push_back(HostProb{L->g.half, n, slot, L->g.Xh, L->g.L[1], L->g.L[2], L->g.L[3], 0});
     max_half = std::max(max_half, L->g.half);
     slot += n;
   }
   R.bh.nslots = nslots;
   R.bh.max_half = max_half;
   R.bh.long12 = probs[0].lat->g.long12 != 0;
-  R.bh.pstride = ceil_div(max_half, kWave);
+  R.bh.pstride = ceil_div(max_half, kWave / 2);  // 32-site partials of the time-streaming kernel
   STAG_HIP_TRY(ctl.probs.ensure(sizeof(ProbDev) * kMaxProb));
   STAG_HIP_TRY(ctl.scal.ensure(sizeof(Scal) * nslots));
   STAG_HIP_TRY(ctl.partial.ensure(sizeof(double) * (size_t)nslots * kPartialSlots * R.bh.pstride));

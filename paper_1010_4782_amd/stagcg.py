@@ -191,21 +191,22 @@ class Lattice:
         return out
 
     def tune_dslash(self, prec: str = "f64", nrhs: int = 1, stream=None):
-        """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, tile_order, us), ...])."""
+        """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, tile_order, t_chunks, us),
+        ...])."""
         best = StagShape()
         all_ = (StagShape * 64)()
         n = C.c_int32(0)
         check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 64, C.byref(n),
                                      _stream(stream)), "stag_tune_dslash")
         def tup(s):
-            return (s.wg, s.rhs_per_lane, s.lds_stage, s.tile_order, s.us)
+            return (s.wg, s.rhs_per_lane, s.lds_stage, s.tile_order, s.t_chunks, s.us)
 
         return tup(best), [tup(all_[i]) for i in range(n.value)]
 
     def set_dslash_shape(self, prec: str, nrhs: int, wg: int, rhs_per_lane: int = 1, lds_stage: int = 0,
-                         tile_order: int = 0):
+                         tile_order: int = 0, t_chunks: int = 1):
         """Pin a Dslash launch shape for (this lattice, nrhs, prec); wg = 0 removes the pinned shape."""
-        sh = StagShape(int(wg), int(rhs_per_lane), int(lds_stage), int(tile_order), 0.0)
+        sh = StagShape(int(wg), int(rhs_per_lane), int(lds_stage), int(tile_order), int(t_chunks), 0.0)
         check(lib().stag_set_dslash_shape(self._h, PREC[prec], int(nrhs), C.byref(sh) if wg else None),
               "stag_set_dslash_shape")
 

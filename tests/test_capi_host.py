@@ -122,14 +122,17 @@ def test_tune_cache_roundtrip(lib, tmp_path):
     """The tuning table loads from and saves to JSON without a GPU; malformed entries are refused."""
     src = tmp_path / "tune.json"
     # an entry without the LDS flag (older files) reads as unstaged
-    src.write_text('{\n  "p2:28x28x28x96/1": [256, 1, 1],\n  "p0:8x8x8x8/8": [128, 8]\n}\n')
+    # (and without the time chunks: 1); a time-streaming entry keeps its chunks
+    src.write_text('{\n  "p2:28x28x28x96/1": [256, 1, 1],\n  "p0:8x8x8x8/8": [128, 8],\n'
+                   '  "p2c:48x48x48x144/8": [64, 8, 0, 2, 4]\n}\n')
     assert lib.stag_tune_cache_load(str(src).encode()) == 0
     out = tmp_path / "out.json"
     assert lib.stag_tune_cache_save(str(out).encode()) == 0
     text = out.read_text()
-    assert '"p2:28x28x28x96/1": [256, 1, 1, 0]' in text and '"p0:8x8x8x8/8": [128, 8, 0, 0]' in text
+    assert '"p2:28x28x28x96/1": [256, 1, 1, 0, 1]' in text and '"p0:8x8x8x8/8": [128, 8, 0, 0, 1]' in text
+    assert '"p2c:48x48x48x144/8": [64, 8, 0, 2, 4]' in text
     bad = tmp_path / "bad.json"
-    for entry in ("[100, 3]", "[256, 1, 2]", "[64, 1, 0, 2]"):
+    for entry in ("[100, 3]", "[256, 1, 2]", "[64, 1, 0, 3]", "[64, 8, 0, 2, 0]"):
         bad.write_text('{\n  "p0:8x8x8x8/8": %s\n}\n' % entry)
         assert lib.stag_tune_cache_load(str(bad).encode()) == 1, entry
     assert lib.stag_tune_cache_load(str(tmp_path / "missing.json").encode()) == 1

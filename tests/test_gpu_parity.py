@@ -350,7 +350,8 @@ def test_dslash_identical_for_every_launch_shape(gpu_lib):
     assert rel(ref.cpu().numpy()[3], dslash_eo(fat, lng, b.cpu().numpy()[3], dims, 1)) > 0  # f16 result exists
     best, timed = lat.tune_dslash("f16", 8)
     assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and best[2] in (0, 1) and len(timed) == 24
-    assert best[3] == 0 and all(t[3] == 0 and t[4] > 0 for t in timed)  # the XCD-block order does not fit Lz = 6
+    # neither the XCD-block order (Lz = 6) nor the time-streaming kernel (72 sites per slice) fits
+    assert best[3] == 0 and all(t[3] == 0 and t[5] > 0 for t in timed)
 
 
 def test_xcd_block_tile_order_is_bitwise_equal(gpu_lib):
@@ -557,3 +558,78 @@ def test_pion_correlator_of_point_source_propagators(gpu_lib):
 
     with pytest.raises((StagError, ValueError)):
         lat.slice_norm2(chi, 4)
+
+
+@pytest.mark.parametrize("dims,long_su3", [((8, 4, 4, 6), True), ((4, 4, 4, 8), True), ((4, 4, 4, 2), True),
+                                           ((8, 8, 4, 4), False), ((16, 4, 4, 4), True)])
+def test_time_streaming_dslash_is_bitwise_equal(gpu_lib, dims, long_su3):
+    """The time-streaming FP16 kernel (8 or 4 RHS per lane, the time extent in 1..Lt/2 chunks) against the
+    site-parallel kernel: the same matrices in the same order, so the same bits, for 8 and 16 RHS and both
+    output parities; on Lt = 2, 4, 6 the time hops wrap one to three times.  Shapes whose site count per
+    slice is not a multiple of the wave's sites are refused."""
+    from paper_1010_4782_amd._lib import StagError
+
+    print(f"time-streaming dslash {dims} long_su3={long_su3}", flush=True)
+    lat, fat, lng = make12(dims, 141, ("f64", "f16")) if long_su3 else make(dims, seed=141, precs=("f64", "f16"))
+    S = dims[0] * dims[1] * dims[2] // 2
+    b = torch.from_numpy(gaussian_source(dims, 142, 16)).cuda()
+    for nrhs in (8, 16):
+        bn = b[:nrhs].contiguous()
+        for par in (0, 1):
+            lat.set_dslash_shape("f16", nrhs, 64, 8)
+            ref = lat.dslash(bn, par, prec="f16")
+            for r in (8, 4):
+                for chunks in range(1, dims[3] // 2 + 1):
+                    if (dims[3] // 2) % chunks:
+                        continue
+                    if S % (64 * r // 8):
+                        with pytest.raises(StagError):
+                            lat.set_dslash_shape("f16", nrhs, 64, r, 0, 2, chunks)
+                        continue
+                    lat.set_dslash_shape("f16", nrhs, 64, r, 0, 2, chunks)
+                    assert torch.equal(lat.dslash(bn, par, prec="f16"), ref), (nrhs, par, r, chunks)
+        lat.set_dslash_shape("f16", nrhs, 0, 1)
+    with pytest.raises(StagError):  # 12 RHS: not a multiple of 8
+        lat.set_dslash_shape("f16", 12, 64, 8, 0, 2, 1)
+    with pytest.raises(StagError):  # FP64 has no time-streaming kernel
+        lat.set_dslash_shape("f64", 8, 64, 8, 0, 2, 1)
+
+
+def test_time_streaming_solve(gpu_lib):
+    """Mixed-precision CG with the time-streaming kernel in its iterations: with 8 RHS per lane its
+    reduction partials are those of a 64-site workgroup, so the solve gives the bits of the site-parallel
+    kernel's; with 4 RHS per lane (32-site partials) it converges to the same true residual (oracle).
+    Per-RHS masses make the right-hand sides stop at different iterations, which exercises the
+    per-lane convergence masks; two lattices in one batch exercise the problem table."""
+    from paper_1010_4782_amd.stagcg import cg_solve_batch
+
+    dims = (8, 8, 4, 8)
+    print("time-streaming solve", flush=True)
+    lat, fat, lng = make12(dims, 151, ("f64", "f16"))
+    b = gaussian_source(dims, 152, 8)
+    bt = torch.from_numpy(b).cuda()
+    masses = [0.05, 0.08, 0.1, 0.2, 0.3, 0.05, 0.12, 0.5]
+    lat.set_dslash_shape("f16", 8, 64, 8)
+    x0, i0 = lat.cg_solve(bt, masses, tol=1e-10, prec="f16")
+    lat.set_dslash_shape("f16", 8, 64, 8, 0, 2, 2)
+    x1, i1 = lat.cg_solve(bt, masses, tol=1e-10, prec="f16")
+    assert torch.equal(x0, x1) and [i["iters"] for i in i0] == [i["iters"] for i in i1]
+    assert len(set(i["iters"] for i in i1)) > 2  # the RHS stopped at different iterations
+    lat.set_dslash_shape("f16", 8, 64, 4, 0, 2, 1)
+    x2, i2 = lat.cg_solve(bt, masses, tol=1e-10, prec="f16")
+    x2 = x2.cpu().numpy()
+    for r, m in enumerate(masses):
+        assert i2[r]["converged"] == 1
+        assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[r], x2[r]) <= 1.05e-10
+    lat.set_dslash_shape("f16", 8, 0, 1)
+    # two lattices in one batch, both in the time-streaming kernel
+    dims2 = (8, 4, 4, 6)
+    lat2, fat2, lng2 = make12(dims2, 153, ("f64", "f16"))
+    b2 = gaussian_source(dims2, 154, 8)
+    from paper_1010_4782_amd._lib import lib
+    xs, infos = cg_solve_batch([(lat, bt, masses, None), (lat2, torch.from_numpy(b2).cuda(), 0.1, None)], tol=1e-10,
+                               prec="f16", autotune=True)
+    assert all(i["converged"] == 1 for i in infos)
+    x2b = xs[1].cpu().numpy()
+    for r in range(8):
+        assert true_residual(lambda v: apply_m(fat2, lng2, v, dims2, 0.1), b2[r], x2b[r]) <= 1.05e-10
