@@ -224,6 +224,18 @@ stag_status stag_pion_correlator(stag_lattice_t lat, const void* chi, int32_t ns
 stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,
                          int32_t nrhs, void* stream);
 
+/* stag_apply_m without any allocation, for callers that cannot allocate device memory (code under
+ * stream or graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result as stag_apply_m (the same kernels, so the same bits).  The odd-parity temporary and the
+ * launch's parameter block live in a fixed array of 64 MiB per GPU, compiled into the library and
+ * held until the process ends; the call only launches kernels (no allocation, memset or host copy).
+ * Limits: 1 <= nrhs <= 64 and nrhs * V/2 * 48 bytes <= 64 MiB - 16 KiB, else STAG_ERR_ARG.
+ * Every lattice and stream on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and give undefined results; calls ordered on
+ * one stream are safe.  Other errors as stag_apply_m. */
+stag_status stag_apply_m_noalloc(stag_lattice_t lat, const double* mass, const void* in, void* out,
+                                 int32_t nrhs, void* stream);
+
 /* Solve M x = b for each right-hand side by the CG of Fig. 1 (prm->prec = STAG_F64),
  * by mixed-precision CG with reliable updates (STAG_F32 / STAG_F16), or by flexible
  * CG with a network preconditioner (prm->precond).  Every solve ends with the

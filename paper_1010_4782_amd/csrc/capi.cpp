@@ -5,6 +5,7 @@
 #include <exception>
 #include <new>
 
+#include "noalloc.h"
 #include "runtime.h"
 
 namespace stag {
@@ -246,6 +247,13 @@ stag_status stag_create_lattice(const int32_t dims[4], int32_t t_antiperiodic, s
   L->device = dev;
   L->g = make_geo(L->dims);
   L->g.antiper = t_antiperiodic;
+  // the fixed workspace of stag_apply_m_noalloc: its address on this device, looked up once
+  hipError_t he = noalloc_init(dev);
+  if (he != hipSuccess) {
+    delete L;
+    set_error(std::string("HIP error: ") + hipGetErrorString(he));
+    return STAG_ERR_HIP;
+  }
   *out = L;
   return STAG_OK;
   STAG_GUARD_END
@@ -426,6 +434,43 @@ stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in,
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh, st));
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh, st));
   return ring_release(lat->ctl, e, st);
+  STAG_GUARD_END
+}
+
+stag_status stag_apply_m_noalloc(stag_lattice_t lat, const double* mass, const void* in, void* out, int32_t nrhs,
+                                 void* stream) {
+  STAG_GUARD_BEGIN
+  stag_status s = check_lattice(lat);
+  if (s != STAG_OK) return s;
+  if (!mass || !in || !out) return arg_error("mass, in and out must not be NULL");
+  if (in == out) return arg_error("in and out must not overlap");
+  if (nrhs < 1 || nrhs > kNoAllocMaxRhs) return arg_error("stag_apply_m_noalloc: nrhs must be in [1, 64]");
+  for (int r = 0; r < nrhs; ++r)
+    if (!std::isfinite(mass[r])) return arg_error("mass must be finite");
+  const size_t tmp = spinor_field_bytes(lat, P64, nrhs);
+  if (tmp > kNoAllocBytes - kNoAllocParamBytes)
+    return arg_error("stag_apply_m_noalloc: nrhs x V/2 x 48 bytes exceeds the fixed workspace (64 MiB - 16 KiB)");
+  unsigned char* base = nullptr;
+  STAG_HIP_TRY(noalloc_address(lat->device, &base));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  ProbDev pd = prob_dev(lat, nrhs, 0);
+  pd.vec[V_D] = const_cast<void*>(in);
+  pd.vec[V_AD] = out;
+  pd.vec[V_TMPO] = base + kNoAllocParamBytes;
+  STAG_HIP_TRY(noalloc_write_params(base, pd, mass, nrhs, st));
+  BatchHost bh;
+  bh.probs.assign(1, HostProb{pd.g.half, nrhs, 0, pd.g.Xh, pd.g.L[1], pd.g.L[2], pd.g.L[3], pd.g.t_open});
+  bh.d_probs = reinterpret_cast<const ProbDev*>(base);
+  bh.d_scal = reinterpret_cast<Scal*>(base + noalloc_scal_offset());
+  bh.d_partial = nullptr;  // the plain and xpay epilogues write no partial sums
+  bh.pstride = 0;
+  bh.nslots = nrhs;
+  bh.max_half = pd.g.half;
+  bh.long12 = lat->g.long12 != 0;
+  const DslashShape sh = lookup_shape(bh, single_key(bh, lat, P64), P64);
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh, st));
+  STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh, st));
+  return STAG_OK;
   STAG_GUARD_END
 }
 

@@ -190,6 +190,18 @@ class Lattice:
         check(lib().stag_apply_m(self._h, m, x.data_ptr(), out.data_ptr(), nrhs, _stream(stream)), "stag_apply_m")
         return out
 
+    def apply_m_noalloc(self, x: torch.Tensor, mass, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """M x through stag_apply_m_noalloc: the library allocates nothing (the caller passes `out`)."""
+        nrhs = self._vec(x, "in")
+        masses = [float(mass)] * nrhs if not isinstance(mass, (list, tuple)) else [float(m) for m in mass]
+        if len(masses) != nrhs:
+            raise ValueError("one mass per right-hand side")
+        self._vec(out, "out")
+        m = (C.c_double * nrhs)(*masses)
+        check(lib().stag_apply_m_noalloc(self._h, m, x.data_ptr(), out.data_ptr(), nrhs, _stream(stream)),
+              "stag_apply_m_noalloc")
+        return out
+
     def tune_dslash(self, prec: str = "f64", nrhs: int = 1, stream=None):
         """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, tile_order, t_chunks, us),
         ...])."""
