@@ -224,6 +224,21 @@ stag_status stag_pion_correlator(stag_lattice_t lat, const void* chi, int32_t ns
 stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in, void* out,
                          int32_t nrhs, void* stream);
 
+/* Link fattening: the one-hop (fat) and three-hop (long) link fields that stag_load_links takes, built
+ * from a thin gauge field.  The paper's operator (Sec. 1 and Sec. 2: the improved staggered action of
+ * the MILC ensembles) uses smeared one-hop links and three-hop Naik links but does not give the
+ * smearing; this is the published asqtad recipe (Orginos, Toussaint and Sugar 1999; Lepage 1999):
+ *   fat_mu  = 5/8 U_mu + 1/16 (3-link staples) + 1/64 (5-link) + 1/384 (7-link) - 1/16 (Lepage paths),
+ *             every path of l links scaled by u0^(1-l) (u0 = 1: no tadpole factor);
+ *   long_mu(n) = U_mu(n) U_mu(n + mu) U_mu(n + 2 mu)  (pass naik = -1/(24 u0^2) to stag_load_links).
+ * Periodic in every direction (the antiperiodic time sign belongs to the operator).  FP64.
+ * thin, fat, lng: device complex128 [4][Lt][Lz][Ly][Lx][3][3] (the stag_load_links layout), pairwise
+ * non-overlapping; fat and lng are written.  Workspace: six link fields (144 B per site each) of
+ * lattice workspace, grown on demand and freed with the lattice.  Asynchronous on `stream`.
+ * The lattice needs no links loaded.  NULL pointers, overlap or u0 not finite and > 0: STAG_ERR_ARG. */
+stag_status stag_fatten_links(stag_lattice_t lat, const void* thin, double u0, void* fat, void* lng,
+                              void* stream);
+
 /* stag_apply_m without any allocation, for callers that cannot allocate device memory (code under
  * stream or graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
  * result as stag_apply_m (the same kernels, so the same bits).  The odd-parity temporary and the

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstagcg.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["pack.hip", "dslash.hip", "dslash_t.hip", "blas.hip", "net.hip", "probe.hip", "noalloc.hip", "solver.cpp", "autotune.cpp", "net.cpp", "capi.cpp"]
+SOURCES = ["pack.hip", "dslash.hip", "dslash_t.hip", "blas.hip", "net.hip", "probe.hip", "noalloc.hip", "fatten.hip", "solver.cpp", "autotune.cpp", "net.cpp", "capi.cpp"]
 
 # Packed FP32 instructions are disabled for all device code: they are not needed
 # for this bandwidth-bound path, and the build must not emit them.

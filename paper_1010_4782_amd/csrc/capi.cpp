@@ -5,6 +5,7 @@
 #include <exception>
 #include <new>
 
+#include "fatten.h"
 #include "noalloc.h"
 #include "runtime.h"
 
@@ -93,6 +94,7 @@ stag_lattice_s::~stag_lattice_s() {
   for (auto& b : lscale) b.release();
   for (auto& b : vec) b.release();
   for (auto& b : io_lo) b.release();
+  fat_ws.release();
   ctl.release();
   for (auto ev : prof_events) (void)hipEventDestroy(ev);
 }
@@ -434,6 +436,29 @@ stag_status stag_apply_m(stag_lattice_t lat, const double* mass, const void* in,
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_PLAIN, 1, V_D, V_TMPO, 0, 0, 3, sh, st));
   STAG_HIP_TRY(launch_dslash(bh, P64, EPI_XPAY, 0, V_TMPO, V_AD, V_D, 0, 3, sh, st));
   return ring_release(lat->ctl, e, st);
+  STAG_GUARD_END
+}
+
+stag_status stag_fatten_links(stag_lattice_t lat, const void* thin, double u0, void* fat, void* lng,
+                              void* stream) {
+  STAG_GUARD_BEGIN
+  if (!lat) return arg_error("lattice is NULL");
+  if (!thin || !fat || !lng) return arg_error("thin, fat and lng must not be NULL");
+  if (!std::isfinite(u0) || u0 <= 0.0) return arg_error("u0 must be finite and > 0");
+  int dev = -1;
+  STAG_HIP_TRY(hipGetDevice(&dev));
+  if (dev != lat->device) return arg_error("the current HIP device is not the lattice's device");
+  const size_t field = (size_t)4 * lat->g.half * 2 * 9 * 16;  // [4][V] 3x3 complex128
+  auto overlap = [field](const void* a, const void* b) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + field && y < x + field;
+  };
+  if (overlap(thin, fat) || overlap(thin, lng) || overlap(fat, lng))
+    return arg_error("thin, fat and lng must not overlap");
+  STAG_HIP_TRY(lat->fat_ws.ensure(fatten_workspace_bytes(lat->dims)));
+  STAG_HIP_TRY(fatten_links(lat->dims, thin, u0, fat, lng, lat->fat_ws.ptr, reinterpret_cast<hipStream_t>(stream)));
+  return STAG_OK;
   STAG_GUARD_END
 }
 

@@ -62,6 +62,7 @@ struct stag_lattice_s {
   stag::DevBuf lscale[2];             // f16 link scales per output parity
   stag::DevBuf vec[stag::kNumVec];    // solver workspace per role (grown for the largest nrhs)
   stag::DevBuf io_lo[2];              // low-precision staging for stag_dslash (in, out)
+  stag::DevBuf fat_ws;                // staple fields of stag_fatten_links
   stag::Ctl ctl;
   std::vector<hipEvent_t> prof_events;
   ~stag_lattice_s();

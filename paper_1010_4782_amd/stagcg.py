@@ -121,6 +121,24 @@ class Lattice:
         check(lib().stag_load_links(self._h, fat.data_ptr(), None if lng is None else lng.data_ptr(), float(naik),
                                     mask, _stream(stream)), "stag_load_links")
 
+    def fatten_links(self, thin: torch.Tensor, u0: float = 1.0, fat=None, lng=None, stream=None):
+        """Asqtad one-hop links and three-hop products of a thin gauge field (stag_fatten_links); returns
+        (fat, lng), each complex128 [4][Lt][Lz][Ly][Lx][3][3] on the device."""
+        Lx, Ly, Lz, Lt = self.dims
+        shape = (4, Lt, Lz, Ly, Lx, 3, 3)
+        _dev_tensor(thin, "thin")
+        if tuple(thin.shape) != shape:
+            raise ValueError(f"thin links must have shape {shape}")
+        fat = torch.empty_like(thin) if fat is None else fat
+        lng = torch.empty_like(thin) if lng is None else lng
+        for name, t in (("fat", fat), ("lng", lng)):
+            _dev_tensor(t, name)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} must have shape {shape}")
+        check(lib().stag_fatten_links(self._h, thin.data_ptr(), float(u0), fat.data_ptr(), lng.data_ptr(),
+                                      _stream(stream)), "stag_fatten_links")
+        return fat, lng
+
     def dslash(self, x: torch.Tensor, out_parity: int, prec: str = "f64", out=None, stream=None) -> torch.Tensor:
         nrhs = self._vec(x, "in")
         out = torch.empty_like(x) if out is None else out

@@ -1,0 +1,97 @@
+"""GPU parity of stag_fatten_links (asqtad one-hop links and three-hop products) against the oracle's
+explicit path sums (oracle/fatten.py), elementwise in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.dslash import dslash_eo
+from oracle.fatten import fat_link_at, fat_links, long_link_at, long_links
+from stag_inputs import gaussian_source, random_su3_field, random_su3_field_device
+
+pytestmark = pytest.mark.gpu
+
+# |error| per entry: sums of 85 path products of at most 7 unitary matrices, entries O(1)
+TOL = 1e-12
+
+
+def _fatten(dims, U, u0):
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    lat = Lattice(dims)
+    fat, lng = lat.fatten_links(U, u0)
+    torch.cuda.synchronize()
+    return lat, fat, lng
+
+
+@pytest.mark.parametrize("dims,u0", [((4, 4, 4, 4), 1.0), ((2, 4, 6, 8), 0.87), ((6, 4, 4, 6), 1.0),
+                                     ((4, 2, 2, 4), 0.9), ((2, 2, 2, 2), 1.0)])
+def test_fatten_links_match_oracle(gpu_lib, dims, u0):
+    print(f"fatten dims={dims} u0={u0}", flush=True)
+    U = random_su3_field(dims, 71)
+    _, fat, lng = _fatten(dims, torch.from_numpy(U).cuda(), u0)
+    V = fat_links(U, dims, u0)
+    W = long_links(U, dims)
+    assert np.max(np.abs(fat.cpu().numpy() - V)) <= TOL
+    assert np.max(np.abs(lng.cpu().numpy() - W)) <= TOL
+
+
+def test_fatten_unit_links_closed_form(gpu_lib):
+    dims = (4, 4, 2, 6)
+    U = np.zeros((4, 6, 2, 4, 4, 3, 3), dtype=np.complex128)
+    U[..., :, :] = np.eye(3)
+    for u0 in (1.0, 0.8):
+        _, fat, lng = _fatten(dims, torch.from_numpy(U).cuda(), u0)
+        c = 5 / 8 + 6 / 16 / u0**2 + 24 / 64 / u0**4 + 48 / 384 / u0**6 - 6 / 16 / u0**4
+        assert np.max(np.abs(fat.cpu().numpy() - c * U)) <= TOL
+        assert np.max(np.abs(lng.cpu().numpy() - U)) <= TOL
+
+
+def test_fattened_links_drive_the_operator(gpu_lib):
+    """The fields come out in the layout stag_load_links takes: D with GPU-fattened links equals the
+    oracle's D with oracle-fattened links."""
+    dims, u0 = (4, 4, 4, 6), 0.9
+    U = random_su3_field(dims, 72)
+    lat, fat, lng = _fatten(dims, torch.from_numpy(U).cuda(), u0)
+    naik = -1.0 / (24.0 * u0 * u0)
+    lat.load_links(fat, lng, naik)
+    b = gaussian_source(dims, 73, 2)
+    out = lat.dslash(torch.from_numpy(b).cuda(), 1).cpu().numpy()
+    V = fat_links(U, dims, u0)
+    W = long_links(U, dims)
+    for r in range(2):
+        ref = dslash_eo(V, W, b[r], dims, 1, naik=naik)
+        assert np.linalg.norm(out[r] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_fatten_full_size_28cubed_96_sampled(gpu_lib):
+    dims = (28, 28, 28, 96)
+    print(f"fatten sampled dims={dims}", flush=True)
+    Ud = random_su3_field_device(dims, 74)
+    _, fat, lng = _fatten(dims, Ud, 1.0)
+    U = Ud.cpu().numpy()
+    rng = np.random.default_rng(75)
+    sites = [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(24)]
+    sites += [(0, 0, 0, 0), (27, 27, 27, 95), (27, 0, 13, 95)]  # boundary wraps in every direction
+    for (x, y, z, t) in sites:
+        for mu in range(4):
+            got = fat[mu, t, z, y, x].cpu().numpy()
+            assert np.max(np.abs(got - fat_link_at(U, dims, (x, y, z, t), mu))) <= TOL
+            got = lng[mu, t, z, y, x].cpu().numpy()
+            assert np.max(np.abs(got - long_link_at(U, dims, (x, y, z, t), mu))) <= TOL
+
+
+def test_fatten_argument_errors(gpu_lib):
+    from paper_1010_4782_amd._lib import StagError
+    from paper_1010_4782_amd.stagcg import Lattice
+
+    dims = (2, 2, 2, 2)
+    lat = Lattice(dims)
+    U = torch.from_numpy(random_su3_field(dims, 76)).cuda()
+    for u0 in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(StagError, match="u0"):
+            lat.fatten_links(U, u0)
+    with pytest.raises(StagError, match="overlap"):
+        lat.fatten_links(U, 1.0, fat=U)
+    fat = torch.empty_like(U)
+    with pytest.raises(StagError, match="overlap"):
+        lat.fatten_links(U, 1.0, fat=fat, lng=fat)
