@@ -107,26 +107,39 @@ hipError_t iteration(Run& R, int x_prec, int x_id, double* d_hist) {
   return e;
 }
 
-// Flexible CG with the network preconditioner (FP64 vectors and operator):
+// Flexible CG with the network preconditioner (FP64 vectors):
 //   z = N(r); beta = -<A d_prev, z> / <d_prev, A d_prev>; d = z + beta d;
 //   alpha = <d, r> / <d, A d>; x += alpha d; r -= alpha A d.
-// Every stall_window iterations the host compares ||r|| with its value one window earlier; a slot
-// that did not drop below stall_ratio times that value (or broke down) leaves the phase and the
-// plain-CG passes that follow finish it from its current x.
+// The operator runs in the solve's precision: for FP32/FP16, d is rounded to that storage, A d is
+// computed there (two Dslash launches, <d, A d> in the epilogue) and widened back to FP64, as in the
+// mixed-precision CG.  Its rounding makes the iterated r drift from b - M x, so the host replaces r by
+// the FP64 true residual ("reliable update") once the iterated |r| has dropped by reliable_delta since
+// the last one, and before accepting an iterated convergence.  The direction d is kept (alpha is the
+// exact line search along d for the new r, and the flexible recurrence needs no other relation
+// between d and r); only <d, r> is recomputed.
+// Every stall_window iterations (the first check after the first window) the host compares the
+// smallest r^dag r of the window with the previous window's; a slot that did not drop below
+// stall_ratio^2 times it (or broke down) leaves the phase, and the plain-CG passes that follow finish it
+// from its current x.
 stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb, double* d_hist, std::vector<int>& iters,
-                      std::vector<int>& fell_back) {
+                      std::vector<int>& fell_back, std::vector<int>& n_rel) {
   const int nslots = R.bh.nslots;
   const int half = R.bh.probs[0].half;
   const size_t vb = (size_t)half * 48;
+  const int P = R.prec;
+  const bool lowp = P != P64;
   stag_lattice_s* L = pb.lat;
   char* rbase = reinterpret_cast<char*>(L->vec[V_R].ptr);
   char* zbase = reinterpret_cast<char*>(L->vec[V_Z].ptr);
   const int window = prm.stall_window > 0 ? prm.stall_window : 10;
   const double ratio2 = prm.stall_ratio * prm.stall_ratio;
+  const double drop2 = (lowp && prm.reliable_delta > 0.0) ? prm.reliable_delta * prm.reliable_delta : 0.0;
+  constexpr int kMaxFcgReliable = 64;  // reliable updates per slot before the phase gives the slot up
   STAG_HIP_TRY(pull_scal(R, "fcg-start"));
   std::vector<double> prev(nslots, 0.0);
   std::vector<char> part(nslots, 0);
-  std::vector<int> saved(nslots);
+  std::vector<int> saved(nslots), nrel(nslots, 0);
+  std::vector<char> done(nslots, 0);  // true residual below tol (after a reliable update)
   bool any = false;
   for (int s = 0; s < nslots; ++s) {
     Scal& sc = R.h_scal[s];
@@ -140,6 +153,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     sc.flags = 0;
     sc.br = sc.bi = 0.0;
     sc.dmin = sc.delta;
+    sc.rel_thr = drop2 * sc.delta;
     prev[s] = sc.delta;
     part[s] = 1;
     any = true;
@@ -152,11 +166,27 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
   STAG_HIP_TRY(push_scal(R));
   auto apply_net = [&]() -> hipError_t {
     for (int r = 0; r < nslots; ++r) {
+      if (!part[r]) continue;
       hipError_t e = net_forward(prm.net, rbase + r * vb, zbase + r * vb, R.st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
+  // A d for the running slots, and <d, A d> in partial kind 0
+  auto apply_a = [&]() -> hipError_t {
+    if (!lowp) {
+      hipError_t e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape64, R.st);
+      if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64, R.st);
+      return e;
+    }
+    // d -> V_RL (storage precision), A d -> V_XL, widened into V_AD
+    hipError_t e = launch_copy_vec(R.bh, P64, V_D, P, V_RL, 1, kVecWG, R.st);
+    if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_PLAIN, 1, V_RL, V_T, 0, 0, 1, R.shape, R.st);
+    if (e == hipSuccess) e = launch_dslash(R.bh, P, EPI_XPAY_DOT, 0, V_T, V_XL, V_RL, 0, 1, R.shape, R.st);
+    if (e == hipSuccess) e = launch_copy_vec(R.bh, P, V_XL, P64, V_AD, 1, kVecWG, R.st);
+    return e;
+  };
+  const int dot_wg = lowp ? partial_wg(R.shape) : R.shape64.wg;
   STAG_HIP_TRY(apply_net());
   STAG_HIP_TRY(launch_zero_vec(R.bh, P64, V_D, 1, kVecWG, R.st));
   STAG_HIP_TRY(launch_fcg_dir(R.bh, 1, kVecWG, R.st));  // d = z, <d, r>
@@ -164,12 +194,9 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     for (int i = 0; i < window; ++i) {
       const bool samp = sample_iteration(R);
       hipError_t e = record(R, samp);
-      if (e == hipSuccess) e = launch_dslash(R.bh, P64, EPI_PLAIN, 1, V_D, V_T, 0, 0, 1, R.shape64, R.st);
-      if (e == hipSuccess)
-        e = launch_dslash(R.bh, P64, EPI_XPAY_DOT, 0, V_T, V_AD, V_D, 0, 1, R.shape64, R.st);
+      if (e == hipSuccess) e = apply_a();
       if (e == hipSuccess) e = record(R, samp);
-      if (e == hipSuccess)
-        e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, R.shape64.wg, d_hist, R.hist_len, R.st, kVecWG);
+      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, dot_wg, d_hist, R.hist_len, R.st, kVecWG);
       if (e == hipSuccess) e = launch_fcg_update(R.bh, kVecWG, R.st);
       if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_RES, 1, 1, kVecWG, nullptr, 0, R.st);
       if (e == hipSuccess) e = apply_net();
@@ -179,24 +206,72 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
       STAG_HIP_TRY(e);
     }
     STAG_HIP_TRY(pull_scal(R, "poll-fcg"));
-    bool running = false;
+    // stall test; slots due for a reliable update (iterated |r| dropped, or iterated convergence to check)
+    std::vector<char> due(nslots, 0);
+    bool any_due = false, running = false;
     for (int s = 0; s < nslots; ++s) {
       Scal& sc = R.h_scal[s];
-      if (sc.state != 0) {
-        if (sc.state == 2 && (sc.flags & kFlagBreakdown)) fell_back[s] = 1;
+      if (!part[s] || done[s]) continue;
+      if (sc.state == 2) {  // broke down
+        if (sc.flags & kFlagBreakdown) fell_back[s] = 1;
         continue;
       }
+      if (sc.state == 1 && (sc.flags & kFlagMaxIter)) continue;
       // the residual of a preconditioned CG need not fall monotonically: compare the best r^dag r
       // of this window with the best one window earlier
-      if (sc.dmin > ratio2 * prev[s]) {
+      if (sc.state == 0 && sc.dmin > ratio2 * prev[s]) {
         fell_back[s] = 1;
         sc.state = 2;
-      } else {
-        prev[s] = sc.dmin;
+        continue;
+      }
+      prev[s] = sc.dmin;
+      const bool conv = sc.state == 1;  // iterated residual below the threshold
+      if (lowp && (conv || sc.delta <= sc.rel_thr)) {
+        if (nrel[s] >= kMaxFcgReliable) {
+          sc.state = 1;
+          continue;
+        }
+        due[s] = 1;
+        any_due = true;
+        sc.state = 1;  // the gate of the update kernels; running slots stay in state 0
+      } else if (sc.state == 0) {
         running = true;
       }
     }
     STAG_HIP_TRY(push_scal(R));
+    if (any_due) {
+      // r = b - M x in FP64 for the slots in state 1, then <d, r> with the new r
+      STAG_HIP_TRY(true_residual(R, 4));
+      STAG_HIP_TRY(pull_scal(R, "fcg-reliable"));
+      bool any_restart = false;
+      for (int s = 0; s < nslots; ++s) {
+        if (!due[s]) continue;
+        Scal& sc = R.h_scal[s];
+        nrel[s] += 1;
+        if (sc.aux <= prm.tol) {
+          sc.state = 3;  // converged; classified after the phase
+          done[s] = 1;
+          continue;
+        }
+        // continue from the true residual; the next window must bring r^dag r below stall_ratio^2 of it
+        sc.rel_thr = drop2 * sc.delta;
+        sc.dmin = sc.delta;
+        prev[s] = sc.delta;
+        any_restart = true;
+      }
+      STAG_HIP_TRY(push_scal(R));
+      if (any_restart) {
+        STAG_HIP_TRY(launch_fcg_dir(R.bh, 4, kVecWG, R.st, 1));  // <d, r> for the new r
+        for (int s = 0; s < nslots; ++s)
+          if (due[s] && !done[s]) {
+            R.h_scal[s].state = 0;
+            running = true;
+          }
+      }
+      for (int s = 0; s < nslots; ++s)
+        if (done[s]) R.h_scal[s].state = 1;
+      STAG_HIP_TRY(push_scal(R));
+    }
     if (!running) break;
   }
   // hand the participants back to the outer loop (state 2: classify) and restore the others
@@ -207,6 +282,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
       continue;
     }
     iters[s] += sc.iter;
+    n_rel[s] += nrel[s];
     sc.iter = 0;
     sc.flags &= ~(kFlagBreakdown | kFlagMaxIter);
     sc.state = 2;
@@ -383,7 +459,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
   STAG_HIP_TRY(true_residual(R, 0));
   std::vector<int> fell_back(nslots, 0);
   if (use_net) {
-    stag_status fs = fcg_phase(R, prm, probs[0], d_hist, iters, fell_back);
+    stag_status fs = fcg_phase(R, prm, probs[0], d_hist, iters, fell_back, n_rel);
     if (fs != STAG_OK) return fs;
     STAG_HIP_TRY(true_residual(R, 0));
   }

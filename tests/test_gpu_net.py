@@ -1,4 +1,6 @@
 """GPU parity of the network preconditioner and of flexible CG against the oracle."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,6 +19,26 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def fp32_bound(Ft32, W32, r32, dims):
+    """Elementwise bound on |GPU - oracle| (real and imaginary part each) for the FP32 network on the same
+    FP32 links, weights and input.  Every real output of a layer is a sum of at most
+    n = 9 directions x C_in channels x 3 colours x 4 real products (w U v), accumulated in binary32:
+    its error is at most gamma_n = n u / (1 - n u), u = 2^-24, times the sum of the terms' magnitudes.
+    That sum is bounded by the same network run on the magnitudes |Re| + |Im| of links, weights and
+    input, in FP64; the layers add their errors, so the output bound is layers x gamma_n x that run."""
+    mag = lambda a: (np.abs(a.real) + np.abs(a.imag)).astype(np.complex128)
+    cin = max(w.shape[2] for w in W32)
+    n = 9 * cin * 3 * 4
+    gamma = n * 2.0**-24 / (1 - n * 2.0**-24)
+    m = net_forward(mag(Ft32), [mag(w) for w in W32], mag(r32), dims).real
+    return len(W32) * gamma * m
+
+
+def assert_within(out, ref, bound):
+    assert np.all(np.abs(out.real - ref.real) <= bound) and np.all(np.abs(out.imag - ref.imag) <= bound), \
+        f"max excess {np.max(np.maximum(np.abs(out.real - ref.real), np.abs(out.imag - ref.imag)) / bound):.3g} of the bound"
+
+
 def setup(dims, seed):
     from paper_1010_4782_amd.stagcg import Lattice
 
@@ -29,11 +51,8 @@ def setup(dims, seed):
 @pytest.mark.parametrize("dims,channels", [((4, 4, 4, 8), [1, 4, 4, 1]), ((6, 4, 4, 6), [1, 8, 8, 8, 1]),
                                            ((4, 2, 6, 4), [1, 2, 1]), ((4, 4, 4, 4), [1, 1])])
 def test_net_forward_matches_oracle(gpu_lib, dims, channels):
-    """FP32 network vs the FP64 oracle on FP32-rounded links and weights.
-
-    Each output is a sum over at most 9 directions x 8 channels x 3 colours of complex products per
-    layer, accumulated in binary32: with four layers the relative error stays below
-    4 x 216 x 2^-24 ~ 5e-5 in the worst case; 2e-5 normwise is the test bound."""
+    """FP32 network vs the FP64 oracle on FP32-rounded links and weights, every element within the
+    rounding bound of fp32_bound."""
     from paper_1010_4782_amd.stagcg import Net
 
     print(f"net forward {dims} {channels}", flush=True)
@@ -49,8 +68,9 @@ def test_net_forward_matches_oracle(gpu_lib, dims, channels):
     out = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
     Ft = quant.to_f32(folded_fat(fat, dims))
     for k in range(2):
-        ref = net_forward(Ft, W32, quant.to_f32(r[k]), dims)
-        assert rel(out[k], ref) <= 2e-5
+        r32 = quant.to_f32(r[k])
+        ref = net_forward(Ft, W32, r32, dims)
+        assert_within(out[k], ref, fp32_bound(Ft, W32, r32, dims))
 
 
 @pytest.mark.parametrize("dims,width", [((4, 4, 2, 6), 4), ((6, 4, 2, 6), 8)])
@@ -114,8 +134,18 @@ def test_fcg_identity_network_is_cg(gpu_lib):
     x0, i0 = lat.cg_solve(bt, m)
     x1, i1 = lat.cg_solve(bt, m, net=net, stall_window=10)
     assert i1[0]["converged"] == 1 and i1[0]["fell_back"] == 0
-    assert abs(i1[0]["iters"] - i0[0]["iters"]) <= max(5, 0.05 * i0[0]["iters"])
-    assert true_residual(lambda v: apply_m(fat, lng, v, dims, m), b[0], x1.cpu().numpy()[0]) <= 1.05e-10
+    assert abs(i1[0]["iters"] - i0[0]["iters"]) <= max(5, 0.02 * i0[0]["iters"])
+    A = lambda v: apply_m(fat, lng, v, dims, m)
+    assert true_residual(A, b[0], x1.cpu().numpy()[0]) <= 1.05e-10
+    # the same with the operator in FP32 and FP16 storage: reliable updates bring the true residual down
+    for prec in ("f32", "f16"):
+        lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32", prec))
+        xm, im = lat.cg_solve(bt, m, prec=prec)
+        xf, jf = lat.cg_solve(bt, m, prec=prec, net=net, stall_window=10)
+        assert jf[0]["converged"] == 1 and jf[0]["fell_back"] == 0, (prec, jf[0])
+        assert jf[0]["n_reliable"] >= 1
+        assert jf[0]["iters"] <= 1.5 * im[0]["iters"] + 10, (prec, jf[0]["iters"], im[0]["iters"])
+        assert true_residual(A, b[0], xf.cpu().numpy()[0]) <= 1.05e-10
 
 
 def test_fcg_trained_network_and_forced_fallback(gpu_lib):
@@ -204,5 +234,42 @@ def test_net_forward_full_size_24cubed_48(gpu_lib):
     net.set_weights(W32)
     r = gaussian_source(dims, 42, 1)
     out = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
-    ref = net_forward(quant.to_f32(folded_fat(fat, dims)), W32, quant.to_f32(r[0]), dims)
-    assert rel(out[0], ref) <= 2e-5
+    Ft = quant.to_f32(folded_fat(fat, dims))
+    r32 = quant.to_f32(r[0])
+    ref = net_forward(Ft, W32, r32, dims)
+    assert_within(out[0], ref, fp32_bound(Ft, W32, r32, dims))
+
+
+def test_fcg_trained_network_24cubed_48(gpu_lib):
+    """The learned-preconditioner workload: 24^3 x 48, m = 0.01, 4 layers of 8 channels trained on
+    solver-made pairs (a small set: the test checks the path, not the network's quality), then FCG with
+    the FP64 operator and with the FP16 operator plus reliable updates; the oracle recomputes each
+    true residual."""
+    from paper_1010_4782_amd.stagcg import Lattice, Net
+    from oracle.dslash import apply_m_chunked
+    from stag_inputs import WORKLOADS, workload_links
+
+    w = WORKLOADS[4]
+    dims, m = w["lattices"][0][0], w["masses"][0]
+    print(f"fcg trained network at {dims} m={m}", flush=True)
+    fat, lng = workload_links(4)
+    lat = Lattice(dims)
+    lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f32", "f16"),
+                   long_su3=True)
+    bs = torch.from_numpy(gaussian_source(dims, 43, 8)).cuda()
+    xs, _ = lat.cg_solve(bs, m)
+    net = Net(lat, layers=w["layers"], channels=w["channels"], seed=7)
+    info = net.train(bs, xs, epochs=2, batch=4, lr=2e-3, loss="solution")
+    assert info["loss_last"] < info["loss_first"]
+    b = gaussian_source(dims, 44, 1)
+    bt = torch.from_numpy(b).cuda()
+    workers = min(16, os.cpu_count() or 1)
+    for prec in ("f64", "f16"):
+        x, inf = lat.cg_solve(bt, m, prec=prec, net=net, stall_window=10)
+        assert inf[0]["converged"] == 1, (prec, inf[0])
+        xh = x.cpu().numpy()
+        r = b - apply_m_chunked(fat, lng, xh, dims, m, workers=workers)
+        res = float(np.linalg.norm(r) / np.linalg.norm(b))
+        print(f"  {prec}: iters {inf[0]['iters']} fell_back {inf[0]['fell_back']} reliable {inf[0]['n_reliable']} "
+              f"oracle true residual {res:.3e}", flush=True)
+        assert res <= 1.05e-10
