@@ -128,17 +128,19 @@ typedef struct {
                                 neighbours from there (same result); needs
                                 rhs_per_lane x (wg + 3 Lx) x bytes-per-vector <= 64 KiB */
   int32_t tile_order;        /* 0: workgroups take tiles in lattice order (t slowest); 1: the z extent
-                                is cut into 8 blocks, one per XCD, and each XCD sweeps t through its
-                                block, so that its L2 still holds the t-neighbour slices; needs Lz
-                                divisible by 8 and wg dividing Ly x Lx / 2.  Same result.
+                                is cut into 8 t_chunks blocks, t_chunks per XCD, and each XCD sweeps t
+                                through one block after the other, so that its L2 still holds the
+                                t-neighbour slices; needs Lz divisible by 8 t_chunks and wg dividing
+                                Ly x Lx / 2.  Same result.
                                 2: time streaming (FP16 only): each wave owns 64 sites of the slice plane
                                 and one time parity and walks t, so that every input slice is used in the
                                 step it is loaded; needs wg 64, rhs_per_lane 8 (one lane per site) or 4
                                 (two lanes per site, 32 sites per wave), nrhs divisible by 8, Lx Ly Lz / 2
                                 divisible by 64 / (8 / rhs_per_lane) and Lt by 2 t_chunks.  Same Dslash
                                 result as 0 and 1 */
-  int32_t t_chunks;          /* tile_order 2: the time extent is walked in this many chunks (1, 2, 4, ...);
-                                otherwise ignored (0 or 1) */
+  int32_t t_chunks;          /* tile_order 1: z blocks per XCD (1, 2, 3, ...); tile_order 2: the time
+                                extent is walked in this many chunks (1, 2, 4, ...); tile_order 0:
+                                ignored (0 or 1) */
   double us;                 /* average launch time (stag_tune_dslash), 0 if not timed */
 } stag_shape;
 

@@ -62,7 +62,10 @@ DslashShape lookup_shape(const BatchHost& bh, const std::string& key, int prec) 
   if (it != g_table.end()) {
     DslashShape s = it->second;
     s.r = std::min(s.r, rhs_divisor(bh));
-    if (!dslash_shape_valid(bh, prec, s)) s.lds = s.order = 0;  // a loaded entry that does not fit this batch
+    if (!dslash_shape_valid(bh, prec, s)) {  // a loaded entry that does not fit this batch
+      s.lds = s.order = 0;
+      s.chunks = 1;
+    }
     return s;
   }
   return heuristic(bh, prec);
@@ -100,6 +103,10 @@ hipError_t tune_batch(const BatchHost& bh, const std::string& key, int prec, hip
   for (int wg : {64, 128, 256})
     for (int r = 1; r <= rmax; r *= 2)
       for (int v = 0; v < 4; ++v) cands.push_back(DslashShape{wg, r, v & 1, v >> 1});
+  // thinner XCD z blocks (2, 3, 4 or 6 per XCD) for the shapes without LDS staging
+  for (int wg : {64, 128})
+    for (int r = 1; r <= rmax; r *= 2)
+      for (int c : {2, 3, 4, 6}) cands.push_back(DslashShape{wg, r, 0, 1, c});
   for (int r : {8, 4})
     for (int chunks : {1, 2, 4}) cands.push_back(DslashShape{64, r, 0, 2, chunks});
   for (const DslashShape& sh : cands) {

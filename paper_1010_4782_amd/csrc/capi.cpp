@@ -621,15 +621,15 @@ stag_status stag_set_dslash_shape(stag_lattice_t lat, int32_t prec, int32_t nrhs
   if (nrhs % r) return arg_error("rhs_per_lane must divide nrhs");
   if (shape->lds_stage != 0 && shape->lds_stage != 1) return arg_error("lds_stage must be 0 or 1");
   if (shape->tile_order < 0 || shape->tile_order > 2) return arg_error("tile_order must be 0, 1 or 2");
-  const int chunks = shape->tile_order == 2 ? shape->t_chunks : 1;
-  if (chunks < 1) return arg_error("t_chunks must be >= 1 with tile_order 2");
+  const int chunks = shape->tile_order != 0 ? shape->t_chunks : 1;
+  if (chunks < 1) return arg_error("t_chunks must be >= 1 with tile_order 1 or 2");
   const DslashShape sh{wg, r, shape->lds_stage, shape->tile_order, chunks};
   if (!dslash_shape_valid(bh, prec, sh))
     return arg_error(sh.order == 2 ? "tile_order 2 needs FP16, wg 64, rhs_per_lane 8 or 4, no LDS staging, nrhs "
                                      "divisible by 8, Lx Ly Lz / 2 divisible by the sites per wave (64 or 32) and Lt "
                                      "by 2 t_chunks"
-                     : sh.order ? "tile_order 1 needs Lz divisible by 8 and wg dividing Ly x Lx / 2 (and, staged, "
-                                  "an LDS window within 64 KiB)"
+                     : sh.order ? "tile_order 1 needs Lz divisible by 8 t_chunks and wg dividing Ly x Lx / 2 (and, "
+                                  "staged, an LDS window within 64 KiB)"
                                 : "the LDS window of this shape exceeds 64 KiB (use fewer sites or RHS per workgroup)");
   pin_shape(key, sh);
   return STAG_OK;

@@ -78,19 +78,21 @@ extern __shared__ __align__(16) char dslash_window[];
 
 __host__ __device__ constexpr int window_margin(int xh) { return 3 * xh; }
 
-// Tile order 1 (XCD blocks): the z extent is cut into kZBlocks blocks, one per XCD, and the workgroups
-// of an XCD (a contiguous range of positions, xcd_remap) sweep t through their block: the colour
-// vectors of the t +-1, +-3 neighbours of a block's slices are then still in that XCD's L2 when they are
-// read again, which the lattice order (t slowest) loses once a slice of all RHS outgrows L2.  Tiles stay
-// contiguous site ranges (a whole number of them per z plane), so every tile is computed exactly as in
-// the lattice order; the shape is valid only where that holds (xcd_order_ok).
+// Tile order 1 (XCD blocks): the z extent is cut into nzb = 8 c blocks (c = the shape's chunks), c per
+// XCD, and the workgroups of an XCD (a contiguous range of positions, xcd_remap) sweep t through one
+// block, then the next: the colour vectors of the t +-1, +-3 neighbours of a block's slices are then
+// still in that XCD's L2 when they are read again, which the lattice order (t slowest) loses once a slice
+// of all RHS outgrows L2.  Thinner blocks keep more of the t window in L2 but read more z neighbours
+// (3 planes on each side) from outside the block; the autotuner picks c.  Tiles stay contiguous site
+// ranges (a whole number of them per z plane), so every tile is computed exactly as in the lattice
+// order; the shape is valid only where that holds (xcd_order_ok).
 constexpr int kZBlocks = 8;
-__host__ __device__ inline bool xcd_order_ok(int ny, int nz, int xh, int wg) {
-  return nz % kZBlocks == 0 && (ny * xh) % wg == 0;
+__host__ __device__ inline bool xcd_order_ok(int ny, int nz, int xh, int wg, int nzb) {
+  return nzb > 0 && nz % nzb == 0 && (ny * xh) % wg == 0;
 }
-__device__ __forceinline__ int xcd_block_tile(int pos, const Geo& g, int wg) {
+__device__ __forceinline__ int xcd_block_tile(int pos, const Geo& g, int wg, int nzb) {
   const int tpz = g.L[1] * g.Xh / wg;  // tiles per z plane
-  const int zbs = g.L[2] / kZBlocks;
+  const int zbs = g.L[2] / nzb;
   const int j = pos % tpz;
   int rest = pos / tpz;
   const int zi = rest % zbs;
@@ -102,7 +104,7 @@ __device__ __forceinline__ int xcd_block_tile(int pos, const Geo& g, int wg) {
 
 template <int P, int R, int EPI, bool C12, int PF, bool LDS>
 __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_id, int out_id, int x_id,
-                                                   int b_id, int gate, int order) {
+                                                   int b_id, int gate, int nzb) {
   static_assert(!(LDS && PF > 0), "the staged path uses the plain link loop");
   using T = typename RealOf<P>::T;
   __shared__ double lds[R * 4];
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
   const int pos = local / groups;
   const int r0 = (local - pos * groups) * R;
   const int nrhs = pd->nrhs, slot0 = pd->slot0;
-  const int tile = order ? xcd_block_tile(pos, g, blockDim.x) : pos;
+  const int tile = nzb ? xcd_block_tile(pos, g, blockDim.x, nzb) : pos;  // nzb 0: lattice order
 
   bool on[R];
   bool any = false;
@@ -380,15 +382,16 @@ static hipError_t dslash_p(const Batch& B, int nblk, int epi, int out_par, int i
 template <int P>
 static hipError_t dslash_pc(const Batch& B, int nblk, int epi, int out_par, int in_id, int out_id, int x_id, int b_id,
                             int gate, const DslashShape& sh, bool c12, size_t lds_bytes, hipStream_t st) {
+  const int nzb = sh.order == 1 ? kZBlocks * sh.chunks : 0;  // z blocks of the XCD order, 0: lattice order
   if (c12)
     return sh.lds ? dslash_p<P, true, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
-                                            sh.order, lds_bytes, st)
+                                            nzb, lds_bytes, st)
                   : dslash_p<P, true, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
-                                             sh.order, 0, st);
+                                             nzb, 0, st);
   return sh.lds ? dslash_p<P, false, true>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
-                                           sh.order, lds_bytes, st)
+                                           nzb, lds_bytes, st)
                 : dslash_p<P, false, false>(B, nblk, epi, out_par, in_id, out_id, x_id, b_id, gate, sh.wg, sh.r,
-                                            sh.order, 0, st);
+                                            nzb, 0, st);
 }
 
 // The LDS window holds wg + 6 Xh sites (of the widest lattice of the batch) per RHS of a lane.
@@ -404,9 +407,10 @@ bool dslash_shape_valid(const BatchHost& bh, int prec, const DslashShape& sh) {
   if (sh.wg != 64 && sh.wg != 128 && sh.wg != 256) return false;
   if (sh.r != 1 && sh.r != 2 && sh.r != 4 && sh.r != 8) return false;
   if (sh.order != 0 && sh.order != 1) return false;
+  if (sh.order == 0 && sh.chunks != 1) return false;
   if (sh.order)
     for (const auto& p : bh.probs)
-      if (!xcd_order_ok(p.ny, p.nz, p.xh, sh.wg)) return false;
+      if (!xcd_order_ok(p.ny, p.nz, p.xh, sh.wg, kZBlocks * sh.chunks)) return false;
   return dslash_lds_bytes(bh, prec, sh) <= kMaxDslashLds;
 }
 

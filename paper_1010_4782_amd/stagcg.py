@@ -224,9 +224,9 @@ class Lattice:
         """Time every Dslash launch shape; returns (best, [(wg, rhs_per_lane, lds_stage, tile_order, t_chunks, us),
         ...])."""
         best = StagShape()
-        all_ = (StagShape * 64)()
+        all_ = (StagShape * 128)()
         n = C.c_int32(0)
-        check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 64, C.byref(n),
+        check(lib().stag_tune_dslash(self._h, PREC[prec], int(nrhs), C.byref(best), all_, 128, C.byref(n),
                                      _stream(stream)), "stag_tune_dslash")
         def tup(s):
             return (s.wg, s.rhs_per_lane, s.lds_stage, s.tile_order, s.t_chunks, s.us)

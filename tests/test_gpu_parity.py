@@ -372,10 +372,26 @@ def test_xcd_block_tile_order_is_bitwise_equal(gpu_lib):
                 assert torch.equal(lat.dslash(b, 0, prec=prec), ref), (prec, r, lds)
         with pytest.raises(StagError):
             lat.set_dslash_shape(prec, 4, 128, 1, 0, 1)  # 128 does not divide the 64 sites of a z plane
+        with pytest.raises(StagError):
+            lat.set_dslash_shape(prec, 4, 64, 1, 0, 1, 2)  # Lz = 8 cannot be cut into 16 blocks
         lat.set_dslash_shape(prec, 4, 0, 1)
     assert rel(ref.cpu().numpy()[1], dslash_eo(fat, lng, b.cpu().numpy()[1], dims, 0)) > 0
     x, info = lat.cg_solve(b, 0.05, tol=1e-10, prec="f16")
     assert all(i["converged"] == 1 for i in info)
+    # thinner blocks: Lz = 48 in 8, 16, 24 or 48 blocks (one z plane per block)
+    dims = (8, 16, 48, 2)
+    lat, _, _ = make(dims, seed=95, precs=("f64", "f16"))
+    b = torch.from_numpy(gaussian_source(dims, 96, 8)).cuda()
+    for prec in ("f64", "f16"):
+        lat.set_dslash_shape(prec, 8, 64, 1)
+        ref = lat.dslash(b, 1, prec=prec)
+        for c in (1, 2, 3, 6):
+            for r in (1, 4, 8):
+                lat.set_dslash_shape(prec, 8, 64, r, 0, 1, c)
+                assert torch.equal(lat.dslash(b, 1, prec=prec), ref), (prec, r, c)
+        with pytest.raises(StagError):
+            lat.set_dslash_shape(prec, 8, 64, 1, 0, 1, 4)  # 48 is not a multiple of 32 blocks
+        lat.set_dslash_shape(prec, 8, 0, 1)
 
 
 def test_batched_solve_with_autotune(gpu_lib):
