@@ -139,9 +139,10 @@ def stream_ceiling(torch, nbytes=4 << 30, reps=10):
             "bytes_read": nbytes, "avg_launch_us": ms * 1e3, "kernel": "k_stream_read (stag_stream_read)"}
 
 
-def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1):
+def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1, shape=None):
     """HBM bytes per Dslash launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source, this workload and this long-link storage; otherwise None."""
+    current kernel source, this workload, this long-link storage and (if the summary names one) this
+    launch shape; otherwise None."""
     import hashlib
 
     tag = f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}" + (f"_{nrhs}rhs" if nrhs > 1 else "")
@@ -150,6 +151,9 @@ def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1):
         return None
     rec = json.load(open(path))
     if rec.get("long_su3", False) != long_su3:
+        return None
+    if "shape" in rec and shape is not None and [shape[k] for k in ("wg", "rhs_per_lane", "lds_stage", "tile_order",
+                                                                   "t_chunks")] != rec["shape"]:
         return None
     h = hashlib.sha256()
     for f in rec["source_files"]:
@@ -246,7 +250,8 @@ class Solves:
                 "reliable_updates": [max(x["n_reliable"] for x in inf) for inf in last],
                 "true_resid": max(x["true_resid"] for inf in last for x in inf),
                 "dslash_shape": {"wg": last[0][0]["dslash_wg"], "rhs_per_lane": last[0][0]["dslash_rhs"],
-                                 "lds_stage": last[0][0]["dslash_lds"], "tile_order": last[0][0]["dslash_order"]}}
+                                 "lds_stage": last[0][0]["dslash_lds"], "tile_order": last[0][0]["dslash_order"],
+                                 "t_chunks": last[0][0]["dslash_chunks"]}}
 
     def shape_name(self):
         return "+".join(f"{p['dims'][0]}^3x{p['dims'][3]}x{p['nrhs']}" if p["dims"][0] == p["dims"][2] else
@@ -358,6 +363,35 @@ def run_learned_preconditioner(a):
     out["break_even_solves"] = (t_data + t_train) / saved if saved > 0 else None
     print(json.dumps(out), flush=True)
     return 0
+
+
+def fattening_leg(dims, reps=2):
+    """stag_fatten_links on the workload's lattice: asqtad one-hop links and three-hop products of a thin
+    SU(3) field drawn on the GPU (the links of the solves are drawn directly, as the recipe says; this times
+    the step that would make them from a gauge configuration)."""
+    import torch
+
+    from paper_1010_4782_amd.stagcg import Lattice
+    from stag_inputs import random_su3_field_device
+
+    U = random_su3_field_device(dims, 77)
+    lat = Lattice(dims)
+    fat, lng = torch.empty_like(U), torch.empty_like(U)
+    lat.fatten_links(U, 1.0, fat, lng)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        lat.fatten_links(U, 1.0, fat, lng)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sites = dims[0] * dims[1] * dims[2] * dims[3]
+    lat.close()
+    del U, fat, lng
+    return {"lattice": list(dims), "ms": ms, "sites_per_s": sites / (ms * 1e-3),
+            "recipe": "asqtad (1, 3, 5, 7-link staples and Lepage paths), u0 = 1, FP64; long = U U U"}
 
 
 def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, fp64_s):
@@ -519,6 +553,9 @@ def main(argv=None):
     ap.add_argument("--loss", default="residual", choices=["residual", "solution"],
                     help="workloads 4 and 5: training loss")
     ap.add_argument("--no-net", action="store_true", help="workload 5: skip the leg with the learned preconditioner")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with one 1 GiB device-to-device copy, the known-size kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 run")
     ap.add_argument("--shard-demo", type=int, default=0, metavar="P",
                     help="instead of the solve: split the workload's first lattice into P time slabs (one per GPU "
                          "of a multi-GPU run), exchange the 3-slice faces on this one GPU, apply the slab Dslash, "
@@ -561,7 +598,8 @@ def main(argv=None):
         fp64 = None
     rate = rec["dslash_" + a.prec]
     d0, n0 = s.probs[0]["dims"], s.probs[0]["nrhs"]
-    traffic = measured_traffic(a.prec, d0, not a.no_long_su3, n0) if len(s.probs) == 1 else None
+    traffic = (measured_traffic(a.prec, d0, not a.no_long_su3, n0, rec["mp_dslash_shape"])
+               if len(s.probs) == 1 else None)
     out = {
         "metric": METRIC, "value": rec["step_s"], "unit": "s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * rec["step_s"], "higher_is_better": False, "scaling": "weak",
@@ -611,6 +649,18 @@ def main(argv=None):
         t_leg = time.perf_counter()
         out["stream_ceiling"] = stream_ceiling(torch)
         legs["stream_ceiling"] = time.perf_counter() - t_leg
+    if big and not a.no_extras:
+        t_leg = time.perf_counter()
+        out["link_fattening"] = fattening_leg(s.w["lattices"][0][0])
+        legs["link_fattening"] = time.perf_counter() - t_leg
+    if a.calibration_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB device to device")
+        del src, dst
     if host is not None:
         log("cpu baseline (oracle) ...")
         t_leg = time.perf_counter()

@@ -115,7 +115,8 @@ typedef struct {
   int32_t dslash_wg;         /* launch shape used by the inner-iteration Dslash: sites per workgroup */
   int32_t dslash_rhs;        /* ... right-hand sides per lane */
   int32_t dslash_lds;        /* ... LDS staging of the x/y neighbour window (1) or not (0) */
-  int32_t dslash_order;      /* ... and the tile order (0 lattice order, 1 XCD blocks) */
+  int32_t dslash_order;      /* ... the tile order (0 lattice order, 1 XCD blocks, 2 time streaming) */
+  int32_t dslash_chunks;     /* ... and its z blocks per XCD (order 1) or time chunks (order 2) */
 } stag_cg_info;
 
 /* A Dslash launch shape and its measured time. */

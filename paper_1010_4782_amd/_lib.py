@@ -65,6 +65,7 @@ class StagInfo(C.Structure):
         ("dslash_rhs", C.c_int32),
         ("dslash_lds", C.c_int32),
         ("dslash_order", C.c_int32),
+        ("dslash_chunks", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

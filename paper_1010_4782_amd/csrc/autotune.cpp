@@ -1,7 +1,7 @@
 // Autotuner for the Dslash launch shape: workgroup size (sites per workgroup),
 // right-hand sides per lane, LDS staging of the x/y neighbour window and the
-// tile order (lattice order or XCD blocks), and, for FP16 batches of 8k right-hand sides, the
-// time-streaming kernel with its number of time chunks.  Candidates are timed with HIP events on the caller's
+// tile order (lattice order, or XCD blocks with their number of z blocks per XCD), and, for FP16
+// batches of 8k right-hand sides, the time-streaming kernel with its number of time chunks.  Candidates are timed with HIP events on the caller's
 // stream on the real buffers of the call; winners are kept per key
 // (lattice shapes, right-hand sides, storage precision) in memory and can be saved
 // to / loaded from a small JSON file.
@@ -38,14 +38,15 @@ int rhs_divisor(const BatchHost& bh) {
   return r;
 }
 
-// Untuned default, from sweeps on 28^3x96 (1-8 RHS, every precision): 64-site workgroups with as many
-// RHS per lane as divide every problem's count (up to 8), unstaged, lattice order.  With the link
-// pipeline of the multi-RHS kernels that is the fastest shape or within 3% of it for 4 and 8 RHS; at
-// 2 RHS FP32 gains 8% from LDS staging, which only the tuner finds.
+// Without a tuned entry: 64-site workgroups, up to 4 RHS per lane (8 needs more registers than a lane
+// has without spilling) and the XCD z-block order where the lattice allows it, the best measured shape
+// on the large lattices; else the lattice order.
 DslashShape heuristic(const BatchHost& bh, int prec) {
   DslashShape s;
-  s.r = rhs_divisor(bh);
+  s.r = std::min(rhs_divisor(bh), 4);
   s.wg = 64;
+  s.order = 1;
+  if (!dslash_shape_valid(bh, prec, s)) s.order = 0;
   if (!dslash_shape_valid(bh, prec, s)) s = DslashShape{64, 1, 0, 0};
   return s;
 }

@@ -633,6 +633,7 @@ stag_status solve_batch(int nprob, const stag_problem* probs, const stag_cg_para
     o.dslash_rhs = R.shape.r;
     o.dslash_lds = R.shape.lds;
     o.dslash_order = R.shape.order;
+    o.dslash_chunks = R.shape.chunks;
     if (first_bad == STAG_OK && done_status[s] != STAG_OK) first_bad = (stag_status)done_status[s];
   }
   if (first_bad != STAG_OK)
