@@ -290,6 +290,16 @@ def solve_record(s: Solves, a, steps, warmup, fp64_steps, extra_precs=()):
     return rec, infos
 
 
+def break_even_stall(mp_solve_s, mp_iters, t_net_s, tol, window=2):
+    """Stall-test parameters under which flexible CG with the network has to keep pace with the
+    mixed-precision CG it would hand over to: a window of `window` FCG iterations (each about one
+    mixed-precision iteration of operator and vector work plus one network application on every RHS)
+    must cut ||r|| at least as much as the mixed-precision solve does in the same time at its average
+    rate (||r|| / ||b|| from 1 to tol in mp_solve_s).  Returns (stall_window, stall_ratio)."""
+    t_it = mp_solve_s / max(1, mp_iters) + t_net_s
+    return window, tol ** (window * t_it / mp_solve_s)
+
+
 def run_learned_preconditioner(a):
     """Workload 4: train the network on (b, x = M^-1 b) pairs made by the batched FP64 solver, then time
     flexible CG with it against plain FP64 CG and mixed-precision CG on the workload's source."""
@@ -330,8 +340,8 @@ def run_learned_preconditioner(a):
     log(f"trained: loss {tinfo['loss_first']:.4f} -> {tinfo['loss_last']:.4f} in {t_train:.1f} s")
     del bs, xs
     res = {}
-    for name, kw in (("fcg_net_" + a.prec, dict(net=net, stall_window=10, prec=a.prec)), ("fp64_cg", {}),
-                     ("mixed_" + a.prec, dict(prec=a.prec))):
+
+    def run(name, kw):
         lat.cg_solve(b_eval, mass, tol=tol, autotune=True, **kw)  # warm-up (and tuning)
         times = []
         for _ in range(max(1, a.steps)):
@@ -341,14 +351,21 @@ def run_learned_preconditioner(a):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t1)
         res[name] = {"s": sum(times) / len(times), "iters": info[0]["iters"], "true_resid": info[0]["true_resid"],
-                     "fell_back": info[0]["fell_back"]}
+                     "fell_back": info[0]["fell_back"], "n_reliable": info[0]["n_reliable"]}
         log(f"{name}: {res[name]}")
+
+    run("fp64_cg", {})
+    run("mixed_" + a.prec, dict(prec=a.prec))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(20):
         net.apply(b_eval)
     torch.cuda.synchronize()
     t_apply = (time.perf_counter() - t1) / 20
+    mp = res["mixed_" + a.prec]
+    win, ratio = break_even_stall(mp["s"], mp["iters"], t_apply, tol)
+    run("fcg_net_" + a.prec, dict(net=net, stall_window=win, stall_ratio=ratio, prec=a.prec))
+    res["fcg_net_" + a.prec]["stall_window"], res["fcg_net_" + a.prec]["stall_ratio"] = win, ratio
     fcg = res["fcg_net_" + a.prec]
     out = {"metric": METRIC, "value": fcg["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
            "ms_per_step": 1e3 * fcg["s"], "higher_is_better": False, "scaling": "weak",
@@ -394,13 +411,14 @@ def fattening_leg(dims, reps=2):
             "recipe": "asqtad (1, 3, 5, 7-link staples and Lepage paths), u0 = 1, FP64; long = U U U"}
 
 
-def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, fp64_s):
+def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, mp_iters, fp64_s):
     """The third change on the large workload: mixed precision, multi-RHS and the learned preconditioner
     together.  The network is trained on the 24^3x48 lattice (links drawn by the same recipe) at this
     workload's mass, then its weights (the layers are gauge-covariant stencils with site-independent
     channel weights, so they do not depend on the volume) are loaded into a network on the large
     lattice.  The solve is flexible CG with the network on all RHS, which hands each RHS to the
-    mixed-precision CG when its residual stalls."""
+    mixed-precision CG when its residual stalls; the stall test asks it to keep pace with the
+    mixed-precision CG measured before (break_even_stall)."""
     import torch
 
     from paper_1010_4782_amd.stagcg import Lattice, Net
@@ -439,20 +457,25 @@ def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, fp64_s):
     lat.load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
     net = Net(lat, layers=w4["layers"], channels=w4["channels"], seed=1, hermitian=True)
     net.set_weights(weights)
-    kw = dict(tol=tol, prec=a.prec, reliable_interval=rel_int, net=net, stall_window=10, autotune=True)
+    net.apply(p["b"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net.apply(p["b"])
+    torch.cuda.synchronize()
+    t_apply = time.perf_counter() - t1
+    win, ratio = break_even_stall(mp_s, mp_iters, t_apply, tol)
+    kw = dict(tol=tol, prec=a.prec, reliable_interval=rel_int, net=net, stall_window=win, stall_ratio=ratio,
+              autotune=True)
     lat.cg_solve(p["b"], mass, **kw)  # warm-up
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     _, info = lat.cg_solve(p["b"], mass, **kw)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t1
-    t1 = time.perf_counter()
-    net.apply(p["b"])
-    torch.cuda.synchronize()
-    t_apply = time.perf_counter() - t1
     net.close()
     res = {"solve_s": t_solve, "iters": max(i["iters"] for i in info), "fell_back": sum(i["fell_back"] for i in info),
            "true_resid": max(i["true_resid"] for i in info), "network_apply_ms_all_rhs": 1e3 * t_apply,
+           "stall_window": win, "stall_ratio": ratio,
            "speedup_vs_mixed_only": mp_s / t_solve, "speedup_vs_fp64_cg": (fp64_s / t_solve) if fp64_s else None,
            "training": {"lattice": list(dims4), "pairs": npairs, "epochs": a.epochs, "data_s": t_data,
                         "train_s": t_train, "loss_first": tinfo["loss_first"], "loss_last": tinfo["loss_last"]}}
@@ -636,7 +659,7 @@ def main(argv=None):
         if not a.no_net:
             t_leg = time.perf_counter()
             out["with_network"] = network_leg(a, s, s.w["masses"][0], s.tol, s.rel_int, rec["solve_s"],
-                                              fp64["solve_s"] if fp64 else None)
+                                              max(rec["mp_iters"]), fp64["solve_s"] if fp64 else None)
             legs["with_network"] = time.perf_counter() - t_leg
         s.close()
         t_leg = time.perf_counter()
