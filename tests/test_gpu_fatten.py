@@ -80,6 +80,27 @@ def test_fatten_full_size_28cubed_96_sampled(gpu_lib):
             assert np.max(np.abs(got - long_link_at(U, dims, (x, y, z, t), mu))) <= TOL
 
 
+def test_fatten_full_size_48cubed_144_sampled(gpu_lib):
+    """The largest single-GPU lattice (the 8-RHS workload's): 63.7 M links per direction field."""
+    dims = (48, 48, 48, 144)
+    print(f"fatten sampled dims={dims}", flush=True)
+    Ud = random_su3_field_device(dims, 78)
+    _, fat, lng = _fatten(dims, Ud, 0.9)
+    U = Ud.cpu().numpy()
+    del Ud
+    rng = np.random.default_rng(79)
+    sites = [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(12)]
+    sites += [(0, 0, 0, 0), (47, 47, 47, 143), (1, 46, 0, 142)]
+    for (x, y, z, t) in sites:
+        for mu in range(4):
+            got = fat[mu, t, z, y, x].cpu().numpy()
+            assert np.max(np.abs(got - fat_link_at(U, dims, (x, y, z, t), mu, 0.9))) <= TOL
+            got = lng[mu, t, z, y, x].cpu().numpy()
+            assert np.max(np.abs(got - long_link_at(U, dims, (x, y, z, t), mu))) <= TOL
+    del fat, lng
+    torch.cuda.empty_cache()
+
+
 def test_fatten_argument_errors(gpu_lib):
     from paper_1010_4782_amd._lib import StagError
     from paper_1010_4782_amd.stagcg import Lattice
