@@ -139,10 +139,21 @@ def stream_ceiling(torch, nbytes=4 << 30, reps=10):
             "bytes_read": nbytes, "avg_launch_us": ms * 1e3, "kernel": "k_stream_read (stag_stream_read)"}
 
 
+def long12_for(a, prec: str, max_nrhs: int) -> bool:
+    """Three-hop link storage of a leg: two rows (12 reals, the third rebuilt in the kernel) or all 18.
+    auto: 12 reals for FP64 and for fewer than 8 RHS per lattice, where the launch is bound by its bytes;
+    18 reals for a mixed-precision leg of 8 or more RHS per lattice, where the rebuild's arithmetic costs
+    more than its 96 saved bytes per site (measured: 8-RHS FP16 launch at 48^3x144, 1630 against 1841 us)."""
+    if a.long_links == "12":
+        return True
+    if a.long_links == "18":
+        return False
+    return prec == "f64" or max_nrhs < 8
+
+
 def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1, shape=None):
     """HBM bytes per Dslash launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source, this workload, this long-link storage and (if the summary names one) this
-    launch shape; otherwise None."""
+    current kernel source, this workload, this long-link storage and this launch shape; otherwise None."""
     import hashlib
 
     tag = f"dslash_{prec}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}" + (f"_{nrhs}rhs" if nrhs > 1 else "")
@@ -150,15 +161,17 @@ def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1, shape=None)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("long_su3", False) != long_su3:
-        return None
-    if "shape" in rec and shape is not None and [shape[k] for k in ("wg", "rhs_per_lane", "lds_stage", "tile_order",
-                                                                   "t_chunks")] != rec["shape"]:
-        return None
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    # traffic per long-link storage and launch shape: "l12:wg,rhs_per_lane,lds_stage,tile_order,t_chunks"
+    if shape is None:
+        return None
+    key = ("l12:" if long_su3 else "l18:") + ",".join(
+        str(shape[k]) for k in ("wg", "rhs_per_lane", "lds_stage", "tile_order", "t_chunks"))
+    return rec["traffic_bytes_per_launch"].get(key)
 
 
 def log(msg):
@@ -188,6 +201,9 @@ class Solves:
             self.host.append(b if keep_host else None)
         torch.cuda.synchronize()
 
+    def long12(self, prec):
+        return long12_for(self.a, prec, max(p["nrhs"] for p in self.probs))
+
     def host_links(self, li=0):
         return self.probs[li]["fat"].cpu().numpy(), self.probs[li]["lng"].cpu().numpy()
 
@@ -199,7 +215,9 @@ class Solves:
 
         precs = precs or ("f64", prec)
         for p in self.probs:
-            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=not self.a.no_long_su3)
+            p["lat"].load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=precs, long_su3=self.long12(prec))
+            if self.a.shape and prec != "f64":
+                p["lat"].set_dslash_shape(prec, p["nrhs"], *self.a.shape)
         torch.cuda.synchronize()  # load_links is asynchronous; keep its packing out of solve_s
         infos, t_solve = [], 0.0
         for m in self.w["masses"]:
@@ -238,7 +256,7 @@ class Solves:
         flat = [inf for infos_ in infos for inf in infos_]
         ms = sum(i[0]["dslash_ms"] for i in flat)
         calls = sum(i[0]["dslash_calls"] for i in flat)
-        per_launch = sum(launch_bytes(prec, p["lat"].half, p["nrhs"], not self.a.no_long_su3) for p in self.probs)
+        per_launch = sum(launch_bytes(prec, p["lat"].half, p["nrhs"], self.long12(prec)) for p in self.probs)
         avg = ms / max(calls, 1)
         sites = sum(p["lat"].half * p["nrhs"] for p in self.probs)
         return dict(GBps=per_launch / (avg * 1e-3) / 1e9, avg_launch_us=avg * 1e3, bytes_per_launch=per_launch,
@@ -316,7 +334,7 @@ def run_learned_preconditioner(a):
     b_eval = torch.from_numpy(workload_sources(4)).cuda()
     lat = Lattice(dims)
     lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0,
-                   precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
+                   precs=("f64", "f32", a.prec), long_su3=long12_for(a, a.prec, 1))
     del fat, lng
     half = lat.half
     chunk = 8
@@ -430,7 +448,7 @@ def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, mp_iters, fp64_s):
     fat, lng = workload_links(4)
     small = Lattice(dims4)
     small.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), -1.0 / 24.0,
-                     precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
+                     precs=("f64", "f32", a.prec), long_su3=long12_for(a, a.prec, 8))
     del fat, lng
     bs = torch.empty((npairs, small.half, 3), dtype=torch.complex128, device="cuda")
     xs = torch.empty_like(bs)
@@ -454,7 +472,7 @@ def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, mp_iters, fp64_s):
     small.close()
     p = s.probs[0]
     lat = p["lat"]
-    lat.load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=("f64", "f32", a.prec), long_su3=not a.no_long_su3)
+    lat.load_links(p["fat"], p["lng"], -1.0 / 24.0, precs=("f64", "f32", a.prec), long_su3=s.long12(a.prec))
     net = Net(lat, layers=w4["layers"], channels=w4["channels"], seed=1, hermitian=True)
     net.set_weights(weights)
     net.apply(p["b"])
@@ -504,7 +522,7 @@ def run_shard_demo(a):
     fat, lng = workload_links_device(a.workload)
     b = torch.from_numpy(workload_sources(a.workload)).cuda()
     lat = Lattice(dims)
-    lat.load_links(fat, lng, -1.0 / 24.0, precs=("f64",), long_su3=not a.no_long_su3)
+    lat.load_links(fat, lng, -1.0 / 24.0, precs=("f64",), long_su3=long12_for(a, "f64", 1))
     del fat, lng
     S = lat.half // Lt
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -567,8 +585,13 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape instead of timing the candidates (for "
                          "counter-collection runs, where every dispatch is serialised and timings mean nothing)")
-    ap.add_argument("--no-long-su3", action="store_true",
-                    help="store the three-hop links with all 18 reals instead of two rows (12 parameters)")
+    ap.add_argument("--long-links", default="auto", choices=["auto", "12", "18"],
+                    help="three-hop link storage: two rows (12 reals, third rebuilt) or all 18; auto: 12 for FP64 "
+                         "and fewer than 8 RHS per lattice, 18 for a mixed-precision leg of 8 or more")
+    ap.add_argument("--no-long-su3", action="store_true", help="same as --long-links 18")
+    ap.add_argument("--shape", type=lambda v: [int(x) for x in v.split(",")], default=None,
+                    metavar="WG,R,LDS,ORDER,CHUNKS",
+                    help="pin the mixed-precision Dslash launch shape (for counter runs without the tuner)")
     ap.add_argument("--train-pairs", type=int, default=0,
                     help="workloads 4 and 5: training pairs (0: 2000 for workload 4, 256 for workload 5)")
     ap.add_argument("--epochs", type=int, default=5, help="workloads 4 and 5: training epochs")
@@ -584,6 +607,8 @@ def main(argv=None):
                          "of a multi-GPU run), exchange the 3-slice faces on this one GPU, apply the slab Dslash, "
                          "check the assembled result against the unsplit one and time both")
     a = ap.parse_args(argv)
+    if a.no_long_su3:
+        a.long_links = "18"
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU runs are not supported.",
               file=sys.stderr)
@@ -621,7 +646,7 @@ def main(argv=None):
         fp64 = None
     rate = rec["dslash_" + a.prec]
     d0, n0 = s.probs[0]["dims"], s.probs[0]["nrhs"]
-    traffic = (measured_traffic(a.prec, d0, not a.no_long_su3, n0, rec["mp_dslash_shape"])
+    traffic = (measured_traffic(a.prec, d0, s.long12(a.prec), n0, rec["mp_dslash_shape"])
                if len(s.probs) == 1 else None)
     out = {
         "metric": METRIC, "value": rec["step_s"], "unit": "s", "n_gpus": 1, "steps": a.steps,
@@ -634,7 +659,8 @@ def main(argv=None):
                    "solver": f"mixed-precision CG, {a.prec} storage, FP64 reliable update every {s.rel_int} "
                              f"iterations or after a 10x residual drop, all RHS of a lattice in each launch",
                    "step": "load_links + solve",
-                   "long_links": "18 reals" if a.no_long_su3 else "12 reals (two rows, third rebuilt)"},
+                   "long_links": {leg: ("12 reals (two rows, third rebuilt)" if s.long12(pr) else "18 reals")
+                                  for leg, pr in (("mixed_precision", a.prec), ("fp64_cg", "f64"))}},
         "solve_s": rec["solve_s"],
         "mp_iters": rec["mp_iters"], "mp_reliable_updates": rec["mp_reliable_updates"],
         "mp_true_resid": rec["mp_true_resid"], "dslash_shape": rec["mp_dslash_shape"],

@@ -38,13 +38,15 @@ int rhs_divisor(const BatchHost& bh) {
   return r;
 }
 
-// Without a tuned entry: 64-site workgroups, up to 4 RHS per lane (8 needs more registers than a lane
-// has without spilling) and the XCD z-block order where the lattice allows it, the best measured shape
-// on the large lattices; else the lattice order.
+// Without a tuned entry: the XCD z-block order where the lattice allows it (else the lattice order),
+// and the best measured shape on the large lattices: 64-site workgroups with up to 4 RHS per lane, or,
+// for FP16 with 18-real three-hop links (no third-row rebuild, so 8 RHS fit a lane's registers),
+// 128-site workgroups with up to 8.
 DslashShape heuristic(const BatchHost& bh, int prec) {
   DslashShape s;
-  s.r = std::min(rhs_divisor(bh), 4);
-  s.wg = 64;
+  const bool r8 = prec == P16 && !bh.long12;
+  s.r = std::min(rhs_divisor(bh), r8 ? 8 : 4);
+  s.wg = r8 && s.r == 8 ? 128 : 64;
   s.order = 1;
   if (!dslash_shape_valid(bh, prec, s)) s.order = 0;
   if (!dslash_shape_valid(bh, prec, s)) s = DslashShape{64, 1, 0, 0};

@@ -33,12 +33,14 @@ def test_compulsory_bytes_per_site():
 
 
 def test_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
-    """A counter summary is used only while the kernel sources hash to the value recorded with it and the
-    long-link storage matches (checked on a copy of the sources, so that the test does not depend on
-    whether the committed record was taken on the current kernels)."""
+    """A counter summary is used only while the kernel sources hash to the value recorded with it, the
+    long-link storage matches and it holds the launch shape of the run (checked on a copy of the sources,
+    so that the test does not depend on whether the committed record was taken on the current kernels)."""
     import hashlib
 
     rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_f16_28x28x28x96_traffic.json")))
+    shape = dict(wg=64, rhs_per_lane=1, lds_stage=0, tile_order=0, t_chunks=1)
+    other = dict(shape, wg=128)
     root = tmp_path / "root"
     (root / "profiles").mkdir(parents=True)
     h = hashlib.sha256()
@@ -48,15 +50,16 @@ def test_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
         data = open(os.path.join(ROOT, f), "rb").read()
         dst.write_bytes(data)
         h.update(data)
-    mine = dict(rec, source_sha256=h.hexdigest(), traffic_bytes_per_launch=123.0)
+    mine = dict(rec, source_sha256=h.hexdigest(), traffic_bytes_per_launch={"l12:64,1,0,0,1": 123.0})
     (root / "profiles" / "dslash_f16_28x28x28x96_traffic.json").write_text(json.dumps(mine))
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"]) == 123.0
-    assert bench.measured_traffic("f16", (28, 28, 28, 96), not rec["long_su3"]) is None
-    assert bench.measured_traffic("f16", (4, 4, 4, 4), True) is None  # no record for this lattice
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), True, 1, shape) == 123.0
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), True, 1, other) is None  # shape not counted
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), False, 1, shape) is None
+    assert bench.measured_traffic("f16", (4, 4, 4, 4), True, 1, shape) is None  # no record for this lattice
     changed = root / rec["source_files"][0]
     changed.write_bytes(changed.read_bytes() + b"\n// changed\n")
-    assert bench.measured_traffic("f16", (28, 28, 28, 96), rec["long_su3"]) is None
+    assert bench.measured_traffic("f16", (28, 28, 28, 96), True, 1, shape) is None
 
 
 def test_cpu_baseline_leg_on_a_tiny_lattice():
