@@ -138,6 +138,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
   STAG_HIP_TRY(pull_scal(R, "fcg-start"));
   std::vector<double> prev(nslots, 0.0);
   std::vector<char> part(nslots, 0);
+  std::vector<char> active(nslots, 0);  // running at the last host poll: the network is applied to these
   std::vector<int> saved(nslots), nrel(nslots, 0);
   std::vector<char> done(nslots, 0);  // true residual below tol (after a reliable update)
   bool any = false;
@@ -156,6 +157,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     sc.rel_thr = drop2 * sc.delta;
     prev[s] = sc.delta;
     part[s] = 1;
+    active[s] = 1;
     any = true;
   }
   if (!any) {
@@ -166,7 +168,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
   STAG_HIP_TRY(push_scal(R));
   auto apply_net = [&]() -> hipError_t {
     for (int r = 0; r < nslots; ++r) {
-      if (!part[r]) continue;
+      if (!active[r]) continue;
       hipError_t e = net_forward(prm.net, rbase + r * vb, zbase + r * vb, R.st);
       if (e != hipSuccess) return e;
     }
@@ -272,6 +274,7 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
         if (done[s]) R.h_scal[s].state = 1;
       STAG_HIP_TRY(push_scal(R));
     }
+    for (int s = 0; s < nslots; ++s) active[s] = part[s] && R.h_scal[s].state == 0;
     if (!running) break;
   }
   // hand the participants back to the outer loop (state 2: classify) and restore the others
