@@ -139,16 +139,18 @@ def stream_ceiling(torch, nbytes=4 << 30, reps=10):
             "bytes_read": nbytes, "avg_launch_us": ms * 1e3, "kernel": "k_stream_read (stag_stream_read)"}
 
 
-def long12_for(a, prec: str, max_nrhs: int) -> bool:
+def long12_for(a, prec: str, nrhs_all) -> bool:
     """Three-hop link storage of a leg: two rows (12 reals, the third rebuilt in the kernel) or all 18.
-    auto: 12 reals for FP64 and for fewer than 8 RHS per lattice, where the launch is bound by its bytes;
-    18 reals for a mixed-precision leg of 8 or more RHS per lattice, where the rebuild's arithmetic costs
-    more than its 96 saved bytes per site (measured: 8-RHS FP16 launch at 48^3x144, 1630 against 1841 us)."""
+    auto: 18 reals for a mixed-precision leg whose lattices all have a multiple of 8 RHS, where a lane can
+    then take 8 RHS and the rebuild's arithmetic costs more than its 96 saved bytes per site (measured:
+    8-RHS FP16 launch at 48^3x144, 1630 us with 18 reals and 8 RHS per lane against 1841 us with 12 reals,
+    whose rebuild only fits 4 per lane); 12 reals otherwise (FP64, and fewer RHS per lane: bound by bytes)."""
     if a.long_links == "12":
         return True
     if a.long_links == "18":
         return False
-    return prec == "f64" or max_nrhs < 8
+    nrhs_all = [nrhs_all] if isinstance(nrhs_all, int) else list(nrhs_all)
+    return prec == "f64" or any(n % 8 for n in nrhs_all)
 
 
 def measured_traffic(prec: str, dims, long_su3: bool, nrhs: int = 1, shape=None):
@@ -202,7 +204,7 @@ class Solves:
         torch.cuda.synchronize()
 
     def long12(self, prec):
-        return long12_for(self.a, prec, max(p["nrhs"] for p in self.probs))
+        return long12_for(self.a, prec, [p["nrhs"] for p in self.probs])
 
     def host_links(self, li=0):
         return self.probs[li]["fat"].cpu().numpy(), self.probs[li]["lng"].cpu().numpy()
@@ -586,8 +588,8 @@ def main(argv=None):
                     help="use the library's default launch shape instead of timing the candidates (for "
                          "counter-collection runs, where every dispatch is serialised and timings mean nothing)")
     ap.add_argument("--long-links", default="auto", choices=["auto", "12", "18"],
-                    help="three-hop link storage: two rows (12 reals, third rebuilt) or all 18; auto: 12 for FP64 "
-                         "and fewer than 8 RHS per lattice, 18 for a mixed-precision leg of 8 or more")
+                    help="three-hop link storage: two rows (12 reals, third rebuilt) or all 18; auto: 18 for a "
+                         "mixed-precision leg whose lattices all have a multiple of 8 RHS, else 12")
     ap.add_argument("--no-long-su3", action="store_true", help="same as --long-links 18")
     ap.add_argument("--shape", type=lambda v: [int(x) for x in v.split(",")], default=None,
                     metavar="WG,R,LDS,ORDER,CHUNKS",
