@@ -7,7 +7,9 @@
 // L_k are the packed, phase-, sign- and c_N-folded matrices (pack.hip).  The
 // link stream is the compulsory traffic (16 x 144 B per site in FP64) and is
 // read with non-temporal loads; neighbour colour vectors come through L1/L2,
-// which the XCD-aware block order keeps local.  The output (and the epilogue's
+// which the XCD-aware block order keeps local.  With 8 right-hand sides the
+// loads of a site's 16 neighbours x R vectors keep the CU's vector-memory
+// address and data units nearly always busy: that, more than HBM, sets the pace.  The output (and the epilogue's
 // one read of x or b per site) also goes non-temporal, so that it does not take
 // L2 lines from the neighbours: 9% off the FP16 launch inside the CG solve.
 #include <algorithm>
