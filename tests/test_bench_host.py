@@ -79,3 +79,18 @@ def test_bad_arguments_are_rejected(argv):
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True, text=True,
                          timeout=120)
     assert res.returncode != 0
+
+
+def test_long_link_storage_per_leg():
+    """auto: 18 reals only for a mixed-precision leg whose lattices all have a multiple of 8 RHS (8 per lane);
+    12 reals for FP64 and for the batched and single-RHS legs; the flags force either."""
+    from types import SimpleNamespace
+
+    auto = SimpleNamespace(long_links="auto")
+    assert bench.long12_for(auto, "f16", [8]) is False
+    assert bench.long12_for(auto, "f16", [16, 8]) is False
+    assert bench.long12_for(auto, "f16", [4, 12, 8]) is True
+    assert bench.long12_for(auto, "f16", 1) is True
+    assert bench.long12_for(auto, "f64", [8]) is True
+    assert bench.long12_for(SimpleNamespace(long_links="12"), "f16", [8]) is True
+    assert bench.long12_for(SimpleNamespace(long_links="18"), "f64", 1) is False
