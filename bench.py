@@ -73,8 +73,8 @@ def host_info():
 
 
 def cpu_workers() -> int:
-    """Threads for the oracle's threaded mode: the cores this process may run on (at most 16, the CPU
-    share of a one-GPU machine)."""
+    """Threads for the oracle's threaded mode: the cores this process may run on, at most 16 (the host
+    share that goes with one GPU of a node)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
