@@ -694,6 +694,8 @@ def main(argv=None):
         s2 = Solves(2, a)
         pl, _ = solve_record(s2, a, a.steps, a.warmup, 5, extra_precs=("f32",) if a.prec == "f16" else ())
         pl["workload"] = f"{s2.shape_name()}, m={s2.w['masses']}"
+        pl["traffic"] = measured_traffic(a.prec, s2.probs[0]["dims"], s2.long12(a.prec), s2.probs[0]["nrhs"],
+                                         pl["mp_dslash_shape"])
         out["paper_lattice"] = pl
         s2.close()
         legs["paper_lattice"] = time.perf_counter() - t_leg
