@@ -23,13 +23,30 @@ from .geometry import eta as eta_field, parity
 NAIK_COEFF = -1.0 / 24.0
 
 
-def site_matrices(fat, lng, dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF):
-    """Return (mats [V/2][16][3][3], nbr [V/2][16]) for the sites of parity out_parity."""
+def output_sites(dims, out_parity: int, cbs=None):
+    """Coordinates [S][4] (x, y, z, t) of the output sites: all sites of parity out_parity in checkerboard
+    order (cbs None), or the sites with checkerboard indices cbs, cb = (x + Lx (y + Ly (z + Lz t))) / 2."""
+    Lx, Ly, Lz, Lt = dims
+    if cbs is None:
+        t, z, y, x = np.nonzero(parity(dims) == out_parity)   # lexicographic order = cb order
+        return np.stack([x, y, z, t], axis=1)
+    cbs = np.asarray(cbs, dtype=np.int64)
+    rest = cbs // (Lx // 2)
+    y = rest % Ly
+    z = (rest // Ly) % Lz
+    t = rest // (Ly * Lz)
+    x = 2 * (cbs % (Lx // 2)) + (y + z + t + out_parity) % 2
+    return np.stack([x, y, z, t], axis=1)
+
+
+def site_matrices(fat, lng, dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF,
+                  cbs=None):
+    """Return (mats [S][16][3][3], nbr [S][16]) for the output sites of parity out_parity: all V/2 of them,
+    or the checkerboard indices cbs (see output_sites)."""
     Lx, Ly, Lz, Lt = dims
     L = np.array(dims)
-    par = parity(dims)
-    t, z, y, x = np.nonzero(par == out_parity)          # lexicographic order = cb order
-    n = np.stack([x, y, z, t], axis=1)
+    n = output_sites(dims, out_parity, cbs)
+    x, y, z, t = n.T
     half = len(x)
     mats = np.zeros((half, 16, 3, 3), dtype=np.complex128)
     nbr = np.zeros((half, 16), dtype=np.int64)
@@ -61,13 +78,12 @@ def site_matrices(fat, lng, dims, out_parity: int, antiperiodic_t: bool = True, 
     return mats, nbr
 
 
-def folded_scalars(dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF):
-    """The real scalar folded into each of the 16 matrices of site_matrices: [V/2][16]
+def folded_scalars(dims, out_parity: int, antiperiodic_t: bool = True, naik: float = NAIK_COEFF, cbs=None):
+    """The real scalar folded into each of the 16 matrices of site_matrices: [S][16]
     (eta_mu(n) s(start, k), times c_N for three-hop matrices and -1 for backward ones)."""
     Lx, Ly, Lz, Lt = dims
-    par = parity(dims)
-    t, z, y, x = np.nonzero(par == out_parity)
-    n = np.stack([x, y, z, t], axis=1)
+    n = output_sites(dims, out_parity, cbs)
+    x, y, z, t = n.T
     out = np.zeros((len(x), 16))
     for mu in range(4):
         e = eta_field(mu, dims)[t, z, y, x]

@@ -4,7 +4,8 @@ rule of Sec. 2) with its own operator, chunked over sites and threaded so that 4
 
 Sizes re-checked here: 28^3x96 (FP16 and FP32 mixed precision, plain FP64), the batched 16^4x4 +
 24^3x48x12 + 32^3x64x8 workload at each of its three masses (every RHS), 48^3x144 with 8 right-hand sides
-(every RHS, plus sampled Dslash sites in the launch shapes the solver uses).
+(every RHS, plus sampled Dslash sites in the launch shapes the solver uses: FP64 against the exact
+operator, FP16 against the operator on identically rounded links and inputs within its rounding bound).
 """
 import os
 
@@ -13,6 +14,7 @@ import pytest
 import torch
 
 from oracle.cg import true_residuals
+from oracle import lowprec
 from oracle.dslash import apply_m_chunked, dslash_at_sites
 
 pytestmark = pytest.mark.gpu
@@ -153,3 +155,56 @@ def test_large_lattice_solve_every_rhs_checked_by_oracle(gpu_lib, c5):
     print("   oracle residuals (chunked, threaded)", flush=True)
     r = oracle_resid(c5["fat"], c5["lng"], c5["dims"], c5["b"], x.cpu().numpy(), c5["mass"])
     check_solution(info, r, c5["tol"])
+
+
+def _f16_sampled_check(lat, fat, lng, b, bt, dims, sample, long12):
+    """FP16 Dslash at the sampled output sites of every RHS, both parities, within the rounding bound of
+    the low-precision model (the operator in FP64 on the identically rounded links and inputs: FP32
+    products over 48 complex terms, FP32 third-row rebuild for 12-real links, binary16 output rounding)."""
+    u32 = 2.0 ** -24
+    c = 300 if long12 else 200
+    outs = []
+    for par in (0, 1):
+        out = lat.dslash(bt, par, prec="f16").cpu().numpy()
+        mats, nbr = lowprec.site_matrices(fat, lng, dims, par, cbs=sample)
+        sc = lowprec.folded_scalars(dims, par, cbs=sample) if long12 else None
+        mats_q = lowprec.round_matrices(mats, "f16", long12=long12, scalars=sc)
+        uniq, inv = np.unique(nbr, return_inverse=True)
+        inv = inv.reshape(nbr.shape)
+        for r in range(b.shape[0]):
+            b_q = lowprec.round_spinor(b[r][uniq], "f16")
+            ref = lowprec.apply_site_matrices(mats_q, inv, b_q)
+            s = np.max(np.abs(np.stack([ref.real, ref.imag], -1)).reshape(len(ref), -1), axis=1)
+            bound = c * u32 * lowprec.abs_bound_terms(mats_q, inv, b_q) + (2.0 ** -11) * s[:, None] * 1.001
+            got = out[r][sample]
+            assert np.all(np.abs(got.real - ref.real) <= bound), (par, r)
+            assert np.all(np.abs(got.imag - ref.imag) <= bound), (par, r)
+            # the result is the rounded operator's, not the exact one
+            assert rel(got, dslash_at_sites(fat, lng, b[r], dims, par, sample)) > 1e-8
+        outs.append(out)
+    return outs
+
+
+def test_large_lattice_f16_dslash_sampled_in_benchmark_shapes(gpu_lib, c5):
+    """48^3x144 x 8 RHS, FP16 storage: the kernel the benchmark times (18-real three-hop links, 128-site
+    workgroups, 8 RHS per lane, XCD z-block order) and the 12-real form in its default shape, against the
+    low-precision oracle at sampled sites (tile edges and wraps included); every other launch shape of
+    the same storage gives bitwise the same result."""
+    lat, fat, lng, b, bt, dims, nrhs = (c5[k] for k in ("lat", "fat", "lng", "b", "bt", "dims", "nrhs"))
+    half = b.shape[1]
+    rng = np.random.default_rng(6)
+    sample = np.concatenate([rng.integers(0, half, 96), np.arange(32), np.arange(half - 32, half),
+                             half // 2 + np.arange(-8, 8)])
+    for long12, shapes in ((False, ((128, 8, 0, 1, 1), (64, 8, 0, 1, 3), (64, 4, 0, 0), (64, 8, 0, 2, 2))),
+                           (True, ((64, 4, 0, 1), (64, 1, 0, 0), (64, 8, 0, 2, 1)))):
+        print(f"48^3x144 sampled f16 dslash, {'12' if long12 else '18'}-real three-hop links", flush=True)
+        lat.load_links(torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda(), NAIK, precs=("f64", "f16"),
+                       long_su3=long12)
+        torch.cuda.empty_cache()
+        lat.set_dslash_shape("f16", nrhs, *shapes[0])
+        outs = _f16_sampled_check(lat, fat, lng, b, bt, dims, sample, long12)
+        for shape in shapes[1:]:
+            lat.set_dslash_shape("f16", nrhs, *shape)
+            for par in (0, 1):
+                assert np.array_equal(lat.dslash(bt, par, prec="f16").cpu().numpy(), outs[par]), shape
+        lat.set_dslash_shape("f16", nrhs, 0, 1)

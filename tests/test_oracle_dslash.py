@@ -223,6 +223,27 @@ def test_twelve_parameter_long_links_rebuild_the_operator(dims):
         np.testing.assert_allclose(apply_site_matrices(reb, nbr, v), dslash_eo(fat, lng, v, dims, par), atol=1e-13)
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 6, 8), (6, 2, 4, 6)])
+def test_site_matrices_at_chosen_sites(dims):
+    """site_matrices / folded_scalars for chosen checkerboard indices are the rows of the whole-lattice
+    ones, and applied to a vector they give the site-by-site operator dslash_at_sites."""
+    from oracle.lowprec import apply_site_matrices, folded_scalars, output_sites, site_matrices
+
+    fat, lng = links(dims, 94)
+    v = gaussian_source(dims, 95)[0]
+    half = int(np.prod(dims)) // 2
+    cbs = np.array([0, half - 1, 5, 3, 5, half // 2 + 1])
+    for par in (0, 1):
+        np.testing.assert_array_equal(output_sites(dims, par, np.arange(half)), output_sites(dims, par))
+        mats, nbr = site_matrices(fat, lng, dims, par)
+        m_s, n_s = site_matrices(fat, lng, dims, par, cbs=cbs)
+        np.testing.assert_array_equal(m_s, mats[cbs])
+        np.testing.assert_array_equal(n_s, nbr[cbs])
+        np.testing.assert_array_equal(folded_scalars(dims, par, cbs=cbs), folded_scalars(dims, par)[cbs])
+        np.testing.assert_allclose(apply_site_matrices(m_s, n_s, v), dslash_at_sites(fat, lng, v, dims, par, cbs),
+                                   atol=1e-13)
+
+
 def test_chunked_operator_matches_whole_lattice_operator():
     """The chunked, threaded M (several right-hand sides, one mass each, ragged last chunk) equals apply_m."""
     from oracle.cg import true_residual, true_residuals
