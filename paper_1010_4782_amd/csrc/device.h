@@ -137,8 +137,11 @@ __device__ __forceinline__ void load_spinor_lds(const char* base, int s, float l
   }
 }
 
-// Store and return the stored (rounded) value in v.
-template <int P, bool NT = false>
+// Store and return the stored (rounded) value in v.  FP16: code = binary16(v / m), m = max |component|;
+// RCP takes the six quotients as v x binary32(1 / m), one division per site instead of six (each
+// quotient then within 2^-23 of v / m, far below the binary16 rounding that follows): the Dslash
+// epilogues, where the divisions are a tenth of the arithmetic.
+template <int P, bool NT = false, bool RCP = false>
 __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]) {
   if constexpr (P == P64) {
     gptr_w<d2v> p = as_global_w<d2v>(base) + 3 * s;
@@ -154,9 +157,16 @@ __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename Rea
     for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     unsigned w0 = 0u, w1 = 0u, w2 = 0u;
     if (m > 0.f) {
-      w0 = pack_h2(v[0].re / m, v[0].im / m);
-      w1 = pack_h2(v[1].re / m, v[1].im / m);
-      w2 = pack_h2(v[2].re / m, v[2].im / m);
+      if constexpr (RCP) {
+        const float inv = 1.f / m;
+        w0 = pack_h2(v[0].re * inv, v[0].im * inv);
+        w1 = pack_h2(v[1].re * inv, v[1].im * inv);
+        w2 = pack_h2(v[2].re * inv, v[2].im * inv);
+      } else {
+        w0 = pack_h2(v[0].re / m, v[0].im / m);
+        w1 = pack_h2(v[1].re / m, v[1].im / m);
+        w2 = pack_h2(v[2].re / m, v[2].im / m);
+      }
     }
     st<u4v, NT>(as_global_w<u4v>(base) + s, u4v{w0, w1, w2, __float_as_uint(m)});
     v[0] = unpack_h2(w0, m);

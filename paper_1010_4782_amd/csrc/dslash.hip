@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
     if (live)
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (on[r]) store_spinor<P, true>(out + r * rstride, cb, acc[r]);
+        if (on[r]) store_spinor<P, true, true>(out + r * rstride, cb, acc[r]);
     return;
   }
 
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kMaxWG) void k_dslash(Batch B, int out_par, int in_
       for (int c = 0; c < 3; ++c) o[c] = Cx<T>{a * xv[c].re - acc[r][c].re, a * xv[c].im - acc[r][c].im};
     }
     if (live) {
-      store_spinor<P, true>(out + r * rstride, cb, o);
+      store_spinor<P, true, true>(out + r * rstride, cb, o);
       if (EPI == EPI_XPAY_DOT) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) part[r] += (double)xv[c].re * (double)o[c].re + (double)xv[c].im * (double)o[c].im;

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kWave) void k_dslash_t(Batch B, int out_par, int in
             // output t - 2 is complete
             const long cb = L.i + (long)to * L.S;
             if (EPI == EPI_PLAIN) {
-              if (on[r]) store_spinor<P16, true>(out + r * rstride, cb, c);
+              if (on[r]) store_spinor<P16, true, true>(out + r * rstride, cb, c);
             } else if (on[r]) {
               const float a4 = (float)B.scal[slot0 + rb + r].mass4;
               const float xs = __uint_as_float(xr[r].w.w);
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kWave) void k_dslash_t(Batch B, int out_par, int in
 #pragma unroll
               for (int cc = 0; cc < 3; ++cc)
                 o[cc] = Cx<float>{a4 * xv[cc].re - c[cc].re, a4 * xv[cc].im - c[cc].im};
-              store_spinor<P16, true>(out + r * rstride, cb, o);
+              store_spinor<P16, true, true>(out + r * rstride, cb, o);
 #pragma unroll
               for (int cc = 0; cc < 3; ++cc)
                 part[r] += (double)xv[cc].re * (double)o[cc].re + (double)xv[cc].im * (double)o[cc].im;
