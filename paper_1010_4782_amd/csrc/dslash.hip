@@ -9,7 +9,8 @@
 // read with non-temporal loads; neighbour colour vectors come through L1/L2,
 // which the XCD-aware block order keeps local.  With 8 right-hand sides the
 // loads of a site's 16 neighbours x R vectors keep the CU's vector-memory
-// address and data units nearly always busy: that, more than HBM, sets the pace.  The output (and the epilogue's
+// address and data units nearly always busy, mostly waiting on lines from
+// beyond L2: the loads each CU keeps in flight, more than HBM, set the pace.  The output (and the epilogue's
 // one read of x or b per site) also goes non-temporal, so that it does not take
 // L2 lines from the neighbours: 9% off the FP16 launch inside the CG solve.
 #include <algorithm>
