@@ -310,7 +310,7 @@ def solve_record(s: Solves, a, steps, warmup, fp64_steps, extra_precs=()):
     return rec, infos
 
 
-def break_even_stall(mp_solve_s, mp_iters, t_net_s, tol, window=2):
+def break_even_stall(mp_solve_s, mp_iters, t_net_s, tol, window=1):
     """Stall-test parameters under which flexible CG with the network has to keep pace with the
     mixed-precision CG it would hand over to: a window of `window` FCG iterations (each about one
     mixed-precision iteration of operator and vector work plus one network application on every RHS)
@@ -383,7 +383,7 @@ def run_learned_preconditioner(a):
     torch.cuda.synchronize()
     t_apply = (time.perf_counter() - t1) / 20
     mp = res["mixed_" + a.prec]
-    win, ratio = break_even_stall(mp["s"], mp["iters"], t_apply, tol)
+    win, ratio = break_even_stall(mp["s"], mp["iters"], t_apply, tol, a.stall_window)
     run("fcg_net_" + a.prec, dict(net=net, stall_window=win, stall_ratio=ratio, prec=a.prec))
     res["fcg_net_" + a.prec]["stall_window"], res["fcg_net_" + a.prec]["stall_ratio"] = win, ratio
     fcg = res["fcg_net_" + a.prec]
@@ -483,7 +483,7 @@ def network_leg(a, s: Solves, mass, tol, rel_int, mp_s, mp_iters, fp64_s):
     net.apply(p["b"])
     torch.cuda.synchronize()
     t_apply = time.perf_counter() - t1
-    win, ratio = break_even_stall(mp_s, mp_iters, t_apply, tol)
+    win, ratio = break_even_stall(mp_s, mp_iters, t_apply, tol, a.stall_window)
     kw = dict(tol=tol, prec=a.prec, reliable_interval=rel_int, net=net, stall_window=win, stall_ratio=ratio,
               autotune=True)
     lat.cg_solve(p["b"], mass, **kw)  # warm-up
@@ -597,6 +597,8 @@ def main(argv=None):
     ap.add_argument("--train-pairs", type=int, default=0,
                     help="workloads 4 and 5: training pairs (0: 2000 for workload 4, 256 for workload 5)")
     ap.add_argument("--epochs", type=int, default=5, help="workloads 4 and 5: training epochs")
+    ap.add_argument("--stall-window", type=int, default=1,
+                    help="workloads 4 and 5: flexible-CG iterations per stall test (break-even ratio scaled to it)")
     ap.add_argument("--lr", type=float, default=2e-3, help="workloads 4 and 5: Adam step size")
     ap.add_argument("--loss", default="residual", choices=["residual", "solution"],
                     help="workloads 4 and 5: training loss")

@@ -207,8 +207,7 @@ __global__ __launch_bounds__(kMaxWG) void k_d_fix(Batch B, int gate) {
 
 // ---- flexible CG (FP64 vectors) ----------------------------------------------------
 // d = z + beta d (complex beta from FIN_FCG_BETA; 0 on the first iteration); partial kinds 1, 2 = Re, Im <d, r>.
-// dot_only: keep d, only recompute <d, r> (after r was replaced by the true residual).
-__global__ __launch_bounds__(kMaxWG) void k_fcg_dir(Batch B, int gate, int dot_only) {
+__global__ __launch_bounds__(kMaxWG) void k_fcg_dir(Batch B, int gate) {
   __shared__ double lds[8];
   VecMap m;
   map_vec_block(B, m);
@@ -220,18 +219,16 @@ __global__ __launch_bounds__(kMaxWG) void k_fcg_dir(Batch B, int gate, int dot_o
     char* dp = vec_ptr<P64>(m, V_D);
     load_spinor<P64>(dp, m.cb, d);
     load_spinor<P64>(vec_ptr<P64>(m, V_R), m.cb, r);
-    if (!dot_only) {
-      load_spinor<P64>(vec_ptr<P64>(m, V_Z), m.cb, z);
+    load_spinor<P64>(vec_ptr<P64>(m, V_Z), m.cb, z);
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        d[c] = Cx<double>{z[c].re + br * d[c].re - bi * d[c].im, z[c].im + br * d[c].im + bi * d[c].re};
-    }
+    for (int c = 0; c < 3; ++c)
+      d[c] = Cx<double>{z[c].re + br * d[c].re - bi * d[c].im, z[c].im + br * d[c].im + bi * d[c].re};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       s[0] += d[c].re * r[c].re + d[c].im * r[c].im;
       s[1] += d[c].re * r[c].im - d[c].im * r[c].re;
     }
-    if (!dot_only) store_spinor<P64>(dp, m.cb, d);
+    store_spinor<P64>(dp, m.cb, d);
   }
   block_sum<2>(s, lds);
   if (threadIdx.x == 0) {
@@ -522,11 +519,11 @@ hipError_t launch_d_fix(const BatchHost& bh, int prec, int gate, int wg, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st, int dot_only) {
+hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st) {
   const Batch B = make_batch(bh, wg, 1);
   const int nb = nblocks(B);
   if (nb == 0) return hipSuccess;
-  k_fcg_dir<<<nb, wg, 0, st>>>(B, gate, dot_only);
+  k_fcg_dir<<<nb, wg, 0, st>>>(B, gate);
   return hipGetLastError();
 }
 

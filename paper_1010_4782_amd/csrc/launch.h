@@ -96,8 +96,7 @@ enum Fin : int {
   FIN_FCG_BETA = 9   // kinds 1,2 = Re<Ad,z>, Im<Ad,z>: beta = -<Ad,z>/<d,Ad>
 };
 // Flexible CG vector stages (FP64; z, d, r, Ad, x are the V_Z, V_D, V_R, V_AD, V_X roles).
-hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st,      // d = z + beta d ; <d,r>
-                          int dot_only = 0);                                           // (dot_only: <d,r> only)
+hipError_t launch_fcg_dir(const BatchHost& bh, int gate, int wg, hipStream_t st);      // d = z + beta d ; <d,r>
 hipError_t launch_fcg_update(const BatchHost& bh, int wg, hipStream_t st);            // x += a d ; r -= a Ad ; |r|^2
 hipError_t launch_fcg_beta_dot(const BatchHost& bh, int gate, int wg, hipStream_t st); // <Ad, z>
 // Mixed precision, after a reliable update: restore <d, r> = |r|^2 for the new residual r.

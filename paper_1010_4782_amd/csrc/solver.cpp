@@ -188,23 +188,31 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
     if (e == hipSuccess) e = launch_copy_vec(R.bh, P, V_XL, P64, V_AD, 1, kVecWG, R.st);
     return e;
   };
+  // the next direction of the running slots: z = N(r), beta, d = z + beta d and <d, r>
+  auto next_dir = [&]() -> hipError_t {
+    hipError_t e = apply_net();
+    if (e == hipSuccess) e = launch_fcg_beta_dot(R.bh, 1, kVecWG, R.st);
+    if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_BETA, 1, 1, kVecWG, nullptr, 0, R.st);
+    if (e == hipSuccess) e = launch_fcg_dir(R.bh, 1, kVecWG, R.st);
+    return e;
+  };
   const int dot_wg = lowp ? partial_wg(R.shape) : R.shape64.wg;
   STAG_HIP_TRY(apply_net());
   STAG_HIP_TRY(launch_zero_vec(R.bh, P64, V_D, 1, kVecWG, R.st));
   STAG_HIP_TRY(launch_fcg_dir(R.bh, 1, kVecWG, R.st));  // d = z, <d, r>
+  // A window ends after a residual update, before the network is applied to the new r: a slot that the
+  // stall test hands over costs no network application it would not use, and a reliable update's true
+  // residual is the one the network sees.
   for (;;) {
     for (int i = 0; i < window; ++i) {
       const bool samp = sample_iteration(R);
-      hipError_t e = record(R, samp);
+      hipError_t e = i > 0 ? next_dir() : hipSuccess;
+      if (e == hipSuccess) e = record(R, samp);
       if (e == hipSuccess) e = apply_a();
       if (e == hipSuccess) e = record(R, samp);
       if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_ALPHA, 0, 1, dot_wg, d_hist, R.hist_len, R.st, kVecWG);
       if (e == hipSuccess) e = launch_fcg_update(R.bh, kVecWG, R.st);
       if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_RES, 1, 1, kVecWG, nullptr, 0, R.st);
-      if (e == hipSuccess) e = apply_net();
-      if (e == hipSuccess) e = launch_fcg_beta_dot(R.bh, 1, kVecWG, R.st);
-      if (e == hipSuccess) e = launch_finalize(R.bh, FIN_FCG_BETA, 1, 1, kVecWG, nullptr, 0, R.st);
-      if (e == hipSuccess) e = launch_fcg_dir(R.bh, 1, kVecWG, R.st);
       STAG_HIP_TRY(e);
     }
     STAG_HIP_TRY(pull_scal(R, "poll-fcg"));
@@ -261,21 +269,19 @@ stag_status fcg_phase(Run& R, const stag_cg_params& prm, const stag_problem& pb,
         prev[s] = sc.delta;
         any_restart = true;
       }
-      STAG_HIP_TRY(push_scal(R));
-      if (any_restart) {
-        STAG_HIP_TRY(launch_fcg_dir(R.bh, 4, kVecWG, R.st, 1));  // <d, r> for the new r
+      if (any_restart)
         for (int s = 0; s < nslots; ++s)
           if (due[s] && !done[s]) {
             R.h_scal[s].state = 0;
             running = true;
           }
-      }
       for (int s = 0; s < nslots; ++s)
         if (done[s]) R.h_scal[s].state = 1;
       STAG_HIP_TRY(push_scal(R));
     }
     for (int s = 0; s < nslots; ++s) active[s] = part[s] && R.h_scal[s].state == 0;
     if (!running) break;
+    STAG_HIP_TRY(next_dir());
   }
   // hand the participants back to the outer loop (state 2: classify) and restore the others
   for (int s = 0; s < nslots; ++s) {
