@@ -140,7 +140,8 @@ __device__ __forceinline__ void load_spinor_lds(const char* base, int s, float l
 // Store and return the stored (rounded) value in v.  FP16: code = binary16(v / m), m = max |component|;
 // RCP takes the six quotients as v x binary32(1 / m), one division per site instead of six (each
 // quotient then within 2^-23 of v / m, far below the binary16 rounding that follows): the Dslash
-// epilogues, where the divisions are a tenth of the arithmetic.
+// epilogues, where the divisions are a tenth of the arithmetic.  A subnormal m (the edge of a point
+// source's spreading support reaches 1e-39) keeps the six divisions: 1 / m would overflow.
 template <int P, bool NT = false, bool RCP = false>
 __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename RealOf<P>::T> v[3]) {
   if constexpr (P == P64) {
@@ -157,7 +158,7 @@ __device__ __forceinline__ void store_spinor(void* base, long s, Cx<typename Rea
     for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     unsigned w0 = 0u, w1 = 0u, w2 = 0u;
     if (m > 0.f) {
-      if constexpr (RCP) {
+      if (RCP && m >= 0x1p-126f) {
         const float inv = 1.f / m;
         w0 = pack_h2(v[0].re * inv, v[0].im * inv);
         w1 = pack_h2(v[1].re * inv, v[1].im * inv);

@@ -72,6 +72,20 @@ def test_paper_lattice_solve_checked_by_oracle(gpu_lib, c2, prec):
     check_solution(info, r, c2["tol"])
 
 
+def test_point_source_fp16_solve_28cubed_96(gpu_lib, c2):
+    """28^3x96, m = 0.0062, a point source in FP16 mixed precision: around iterations 12-14 the smallest
+    site scales of r and d fall to 1e-39 (binary32 subnormals; the FP64 oracle CG shows the same), and the
+    solve still converges to the true residual, which the oracle recomputes."""
+    from stag_inputs import point_sources
+
+    print("28^3x96 point-source f16 solve", flush=True)
+    b = point_sources(c2["dims"], [(3, 5, 7, 11)])
+    x, info = c2["lat"].cg_solve(torch.from_numpy(b).cuda(), c2["mass"], tol=c2["tol"], prec="f16",
+                                 reliable_interval=50)
+    r = oracle_resid(c2["fat"], c2["lng"], c2["dims"], b, x.cpu().numpy(), c2["mass"])
+    check_solution(info, r, c2["tol"])
+
+
 @pytest.mark.parametrize("mass", [0.01, 0.02, 0.05])
 def test_batched_uneven_lattices_every_rhs_checked_by_oracle(gpu_lib, mass):
     """The batched workload at full size, one batch per mass: 16^4 x 4 + 24^3x48 x 12 + 32^3x64 x 8

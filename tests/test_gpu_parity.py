@@ -649,3 +649,29 @@ def test_time_streaming_solve(gpu_lib):
     x2b = xs[1].cpu().numpy()
     for r in range(8):
         assert true_residual(lambda v: apply_m(fat2, lng2, v, dims2, 0.1), b2[r], x2b[r]) <= 1.05e-10
+
+
+@pytest.mark.parametrize("long_su3", [True, False])
+def test_dslash_f16_subnormal_site_scales(gpu_lib, long_su3):
+    """An FP16 input scaled into binary32's subnormal range, as the edge of a point source's support is
+    after a dozen CG iterations (site scales near 1e-39, whose reciprocal overflows): every output is
+    finite and equals the unscaled result scaled down, to the precision subnormal scales keep, in the
+    site-parallel and the time-streaming launches, which agree bit for bit."""
+    dims = (8, 8, 8, 8)
+    print(f"dslash f16 subnormal scales long_su3={long_su3}", flush=True)
+    lat, fat, lng = make12(dims, 151, ("f64", "f16")) if long_su3 else make(dims, seed=151, precs=("f64", "f16"))
+    b = gaussian_source(dims, 152, 8)
+    sc = 2.0 ** -133
+    bt, bs = torch.from_numpy(b).cuda(), torch.from_numpy(b * sc).cuda()
+    for par in (0, 1):
+        ref = lat.dslash(bt, par, prec="f16").cpu().numpy()
+        outs = []
+        for shape in ((64, 8, 0, 0), (64, 8, 0, 2, 1)):
+            lat.set_dslash_shape("f16", 8, *shape)
+            out = lat.dslash(bs, par, prec="f16").cpu().numpy()
+            assert np.all(np.isfinite(out.real)) and np.all(np.isfinite(out.imag)), shape
+            assert np.max(np.abs(out)) < 2.0 ** -126  # the output scales are subnormal
+            assert rel(out / sc, ref) <= 1e-3, (par, shape)
+            outs.append(out)
+        assert np.array_equal(outs[0], outs[1]), par
+    lat.set_dslash_shape("f16", 8, 0, 1)
