@@ -70,7 +70,9 @@ template <int P, int R> constexpr int dslash_pf_r() {
   if (R == 1) return dslash_pf<P>();
   if (P == P16) return R == 2 ? 8 : (R == 4 ? 4 : 2);
   if (P == P32) return R == 2 ? 4 : (R == 4 ? 2 : 1);
-  return R == 2 ? 4 : (R == 4 ? 2 : 1);
+  // FP64, measured at 48^3x144 x 8 RHS: 4 and 2 links ahead at R = 4 and 8 (7.1 and 5.6 ms per launch,
+  // against 8.1 and 6.4 ms at 2 and 1, although the deeper pipeline leaves one wave per SIMD at R = 8)
+  return R == 2 ? 4 : (R == 4 ? 4 : 2);
 }
 
 // LDS staging (LDS = true): before the link loop a workgroup copies into LDS the colour vectors of
