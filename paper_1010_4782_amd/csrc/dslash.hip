@@ -69,9 +69,9 @@ template <int P> constexpr int dslash_pf() { return P == P16 ? 12 : (P == P32 ? 
 template <int P, int R> constexpr int dslash_pf_r() {
   if (R == 1) return dslash_pf<P>();
   if (P == P16) return R == 2 ? 8 : (R == 4 ? 4 : 2);
-  if (P == P32) return R == 2 ? 4 : (R == 4 ? 2 : 1);
-  // FP64, measured at 48^3x144 x 8 RHS: 4 and 2 links ahead at R = 4 and 8 (7.1 and 5.6 ms per launch,
-  // against 8.1 and 6.4 ms at 2 and 1, although the deeper pipeline leaves one wave per SIMD at R = 8)
+  // FP32 and FP64, measured at 48^3x144 x 8 RHS: 4 and 2 links ahead at R = 4 and 8 (FP64: 7.1 and
+  // 5.6 ms per launch against 8.1 and 6.4 ms at 2 and 1, although the deeper pipeline leaves one wave
+  // per SIMD at R = 8; FP32: 3.40 and 2.81 ms against 3.46 and 2.91 ms)
   return R == 2 ? 4 : (R == 4 ? 4 : 2);
 }
 
