@@ -84,7 +84,9 @@ typedef struct {
   stag_net_t net;            /* network for STAG_PRECOND_NET (built on the solve's lattice) */
   int32_t stall_window;      /* FCG: every stall_window iterations (default 10) the smallest ||r|| seen so far
                                 is compared with the smallest seen one window earlier; if it did not fall
-                                below stall_ratio times that value, plain CG finishes from the current x */
+                                below stall_ratio times that value, plain CG finishes from the current x.
+                                The test follows the window's last residual update and precedes the next
+                                network application, so a right-hand side handed over costs no extra one */
   double stall_ratio;        /* default 0.9 */
   int32_t profile;           /* k > 0: time the Dslash launches of every k-th inner iteration with HIP events
                                 (stag_cg_info.dslash_ms); each timed iteration idles the GPU for a few us
