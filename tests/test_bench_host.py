@@ -94,3 +94,18 @@ def test_long_link_storage_per_leg():
     assert bench.long12_for(auto, "f64", [8]) is True
     assert bench.long12_for(SimpleNamespace(long_links="12"), "f16", [8]) is True
     assert bench.long12_for(SimpleNamespace(long_links="18"), "f64", 1) is False
+
+
+@pytest.mark.parametrize("window", [1, 2, 5])
+def test_break_even_stall_keeps_pace_with_mixed_precision(window):
+    """The stall ratio asks each flexible-CG window to cut ||r|| as much as the mixed-precision CG does in
+    the same time: windows at exactly that ratio, for as long as the mixed-precision solve takes, reach its
+    tolerance.  A dearer network application or a longer window spans more mixed-precision progress, so
+    it must cut more (a smaller ratio)."""
+    mp_s, iters, t_net, tol = 6.0, 1000, 0.11, 1e-10
+    win, ratio = bench.break_even_stall(mp_s, iters, t_net, tol, window)
+    assert win == window and 0.0 < ratio < 1.0
+    t_window = window * (mp_s / iters + t_net)
+    assert ratio ** (mp_s / t_window) == pytest.approx(tol, rel=1e-9)
+    assert bench.break_even_stall(mp_s, iters, 2 * t_net, tol, window)[1] < ratio
+    assert bench.break_even_stall(mp_s, iters, t_net, tol, window + 1)[1] < ratio
